@@ -1,0 +1,203 @@
+"""Benchmark: reconstructed voxels/s of the hybrid (NUFFT) reconstruction on one
+MI355X, with brute-force BP beside it and the FP64 oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2]
+                       [--precision fp32|bf16|fp16] [--no-cpu] [--no-bp]
+
+One step = one reconstruct_hybrid call (plan tables, scan FFT, range
+compression, back-projection, k_z inverse FFT) over the full echo cube of the
+workload, inputs resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "reconstructed voxels/sec, hybrid-NUFFT vs BP, FP32 vs BF16-MFMA at stated err"
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0               # MI355X published HBM3E bandwidth
+FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def describe(wl) -> str:
+    a = wl.array
+    if a.mode == "mono":
+        arr = f"monostatic polyline {a.n_chords} chords x {a.n_elem} elements on R={a.radius} m"
+    else:
+        arr = f"multistatic polyline {a.n_chords} chords x ({a.n_tx} Tx, {a.n_elem} Rx) on R={a.radius} m"
+    return (f"{arr}, {a.n_scan} scans x {a.scan_step * 1e3:g} mm, {a.n_freq} freqs "
+            f"{a.f_start / 1e9:g}-{a.f_stop / 1e9:g} GHz, image {wl.grid.nx}x{wl.grid.ny}x{a.n_scan}, "
+            f"{wl.scene.n} {wl.scene.kind} scatterers (seed {wl.scene.seed})")
+
+
+def cpu_baseline(wl, echo_np, budget_s=12.0):
+    """The FP64 oracle timed on a bounded sample of the same workload: the
+    exact spectrum at a few (k_z, pixel) pairs, extrapolated to the image."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import geometry as ogeom
+    from oracle import hybrid as ohyb
+    import workloads as W
+
+    arr = ogeom.build(wl.array)
+    npix = wl.grid.nx * wl.grid.ny
+    px, py = ohyb.pixel_grid(wl.grid)
+    S = ohyb.scan_spectrum(echo_np)   # the FFTs: negligible next to the sums
+    n_pix = 256
+    kap = [0]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pix = W.random_subset(npix, n_pix, 99)
+        ohyb.spectrum_at(arr, S, kap, px[pix], py[pix])
+        dt = time.perf_counter() - t0
+        # grow the sample to about budget_s of CPU work
+        scale = max(1, min(64, int(budget_s / max(dt, 1e-3))))
+        pix = W.random_subset(npix, min(npix, n_pix * scale), 98)
+        kap = [0, wl.array.n_scan // 3] if pix.size == npix else [0]
+        t0 = time.perf_counter()
+        ohyb.spectrum_at(arr, S, kap, px[pix], py[pix])
+        dt = time.perf_counter() - t0
+    pairs = len(kap) * pix.size
+    total_pairs = wl.array.n_scan * npix
+    t_full = dt * total_pairs / pairs
+    vox = npix * wl.array.n_scan
+    return {"value": vox / t_full, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": (f"exact spectrum (eq. 7 direct sums) at {pairs} (k_z, pixel) pairs of "
+                       f"{total_pairs}, {dt:.1f} s on 1 thread, extrapolated linearly; "
+                       f"scan FFTs excluded")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bp", action="store_true")
+    ap.add_argument("--bp-planes", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the reconstruction is not sharded across GPUs in this build)", flush=True)
+        return 2
+
+    import torch
+    import paper_2109_02842_amd as pr
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", flush=True)
+        return 1
+    torch.cuda.set_device(0)
+    wl = W.WORKLOADS[args.config]
+    a = wl.array
+    log(f"[bench] {args.config}: {describe(wl)}")
+    geom = pr.make_geometry(a)
+    pos, refl = W.scatterers(wl.scene)
+    echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
+    torch.cuda.synchronize()
+    opts = dict(precision=args.precision)
+    plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
+    ws = pr.workspace(plan.workspace_bytes)
+    img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
+    log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
+        f"tile={plan.tile} du={plan.du * 1e3:.3f} mm workspace={plan.workspace_bytes / 2**20:.1f} MiB")
+
+    # first call: device tables are uploaded lazily (plan build)
+    t0 = time.perf_counter()
+    pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(args.warmup):
+        pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
+    torch.cuda.synchronize()
+    log(f"[bench] warm-up done ({args.warmup} steps)")
+
+    stream = torch.cuda.current_stream()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    for row in evs:
+        for e in row:
+            e.record(stream)   # creates the underlying hipEvent
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        pr.reconstruct_hybrid_events(geom, wl.grid, echo, evs[k], out=img, ws=ws, **opts)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    total_ms = start.elapsed_time(stop)
+    ms = total_ms / args.steps
+    steps_ms = [evs[k][0].elapsed_time(evs[k][5]) for k in range(args.steps)]
+    stage = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
+             for i, name in enumerate(pr.STAGES)}
+    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step (median {np.median(steps_ms):.3f}), wall {wall_ms:.1f} ms; "
+        + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
+
+    voxels = wl.grid.nx * wl.grid.ny * a.n_scan
+    value = voxels / (ms * 1e-3)
+    terms = a.n_scan * wl.grid.nx * wl.grid.ny * geom.n_channels
+    bp_ms = stage["backproject"]
+    achieved = FLOP_PER_TERM * terms / (bp_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
+                   "interp": "bspline4", "l_oversample": 8, "nufft_tol": 1e-6},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "backproject", "flop_per_launch": FLOP_PER_TERM * terms,
+                     "avg_launch_ms": bp_ms},
+        "stages_ms": stage,
+        "plan_build_ms": first_ms,
+    }
+
+    if not args.no_bp:
+        nz = max(1, min(args.bp_planes, a.n_scan))
+        iz0 = a.n_scan // 2 - nz // 2
+        bws = pr.workspace(pr.bp_workspace_bytes(geom))
+        bimg = torch.empty((nz, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
+        pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=1, out=bimg[:1], ws=bws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=nz, out=bimg, ws=bws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1)
+        bp_vps = nz * wl.grid.nx * wl.grid.ny / (bms * 1e-3)
+        out["bp"] = {"value": bp_vps, "unit": "voxels/s", "planes_timed": nz, "ms": bms,
+                     "note": "GPU BP timed on a slab of scan planes; its cost is linear in voxels",
+                     "hybrid_speedup": value / bp_vps}
+        log(f"[bench] BP: {nz} planes in {bms:.1f} ms -> {bp_vps:.3e} voxels/s; hybrid speedup "
+            f"{value / bp_vps:.0f}x")
+
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        echo_np = echo.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(wl, echo_np)
+        log(f"[bench] oracle: {out['cpu_baseline']['value']:.3e} voxels/s")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,306 @@
+/*
+ * polyrecon: near-field millimetre-wave 3-D imaging with polyline arrays on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wang, Li, Zhao, Sun, "Near-Field Millimeter-Wave Imaging via Arrays
+ * in the Shape of Polyline" (arXiv 2109.02842).  The array is a set of equal
+ * chords inscribed in a circle (Sec. II-A, Fig. 1), monostatic or multistatic
+ * (Sec. II-B), mechanically scanned along z.  The reconstruction is the
+ * paper's hybrid time-domain / spatial-frequency method with NUFFT range
+ * compression (eqs. 2-9 monostatic, 12-19 multistatic); brute-force
+ * back-projection (the paper's comparison method, Sec. III) is provided
+ * beside it.
+ *
+ * Conventions shared by every entry point
+ *   - Complex data are interleaved float pairs (re, im), i.e. complex64.
+ *   - "_dev" pointers are device memory on the current HIP device, owned by
+ *     the caller; the library never frees them.  "_host" pointers are host
+ *     memory owned by the caller.
+ *   - Echo cube layout: s[c][m][f] (frequency fastest), c = channel,
+ *     m = scan position, f = frequency.  Channel order: monostatic c = chord *
+ *     n_elem + element; multistatic c = (chord * n_tx + tx) * n_elem + rx.
+ *   - Image layout: g[z][y][x] (x fastest); z runs over the scan grid.
+ *   - Kernels are enqueued on the given stream and return before they
+ *     complete.  A device fault surfaces at the caller's next synchronisation.
+ *   - Return value: PL_OK (0) on success or a negative PL_E* code; the
+ *     message of the last failure on the calling thread is last_error().
+ *   - Geometry handles are immutable after make_geometry and may be shared
+ *     by threads and streams; destroy_geometry must run only after all work
+ *     using the handle has completed.
+ */
+#ifndef POLYRECON_H
+#define POLYRECON_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define PL_OK 0
+#define PL_EINVAL (-1)       /* bad argument: null pointer, size, range      */
+#define PL_EGEOM (-2)        /* no such polyline: chord length >= 2 R        */
+#define PL_EDEVICE (-3)      /* HIP runtime error (allocation, launch)       */
+#define PL_EWORKSPACE (-4)   /* workspace missing or smaller than required   */
+#define PL_EUNSUPPORTED (-5) /* option not supported for this problem        */
+
+#define PL_MONO 0
+#define PL_MULTI 1
+
+/* Sampling-criterion warning bits (set by check_sampling; not errors). */
+#define PL_WARN_ELEMENT_SPACING 1u /* eq. (21) (monostatic: half of it)        */
+#define PL_WARN_SCAN_STEP 2u       /* eq. (22)                                  */
+
+/* ------------------------------------------------------------- geometry */
+/*
+ * Array description (Sec. II-A/B; Table 1 lists the paper's own values).
+ *   mode          PL_MONO or PL_MULTI.
+ *   n_chords      number of polyline sections (>= 1).
+ *   radius_m      radius R_0 of the circumscribed arc (> 0).
+ *   arc_center_rad  angle of the arc's middle; -pi/2 puts the array below the
+ *                 origin looking toward +y.
+ *   n_elem        transceivers per chord (mono) or receivers per chord (multi).
+ *   spacing_m     element / receiver spacing d; chord length is n_elem * d and
+ *                 element j sits at (j + 1/2) d - L/2 from the chord midpoint.
+ *   n_tx          transmitters per chord (multi only; 2 or 4 with the default
+ *                 placement, any count with tx_offsets_m).
+ *   tx_offsets_m  host array of n_tx chord-local Tx offsets from the chord
+ *                 midpoint, or NULL for the default placement at the chord
+ *                 ends (Sec. II-B: -L/2, -L/2 + d/2, L/2 - d/2, L/2 for 4 Tx;
+ *                 -L/2, L/2 for 2 Tx).  Copied by make_geometry.
+ *   n_scan, scan_step_m, scan_z0_m   scan heights z'_m = z0 + m * step.
+ *   n_freq, f_start_hz, f_stop_hz    inclusive uniform sweep (Table 1).
+ */
+typedef struct pl_geometry_desc {
+    int32_t mode;
+    int32_t n_chords;
+    double radius_m;
+    double arc_center_rad;
+    int32_t n_elem;
+    int32_t n_tx;
+    double spacing_m;
+    const double* tx_offsets_m;
+    int32_t n_scan;
+    int32_t n_freq;
+    double scan_step_m;
+    double scan_z0_m;
+    double f_start_hz;
+    double f_stop_hz;
+} pl_geometry_desc;
+
+typedef struct pl_geometry pl_geometry; /* opaque */
+
+typedef struct pl_geometry_info {
+    int32_t mode;
+    int32_t n_chords;
+    int32_t n_channels;
+    int32_t n_scan;
+    int32_t n_freq;
+    int32_t n_tx;
+    int32_t n_elem;
+    int32_t reserved;
+} pl_geometry_info;
+
+/*
+ * Build a polyline array (Sec. II-A/B).  Host-only work; device tables are
+ * uploaded lazily on the first device call on each device.
+ * Errors: PL_EINVAL (null pointers, non-positive sizes, f_start >= f_stop,
+ * n_scan < 1, n_scan > 4096, n_freq > 1024, bad n_tx), PL_EGEOM (chord length
+ * n_elem * spacing >= 2 R_0).  *out is left untouched on failure.
+ */
+int make_geometry(const pl_geometry_desc* desc, pl_geometry** out);
+
+/* Release a handle (NULL is accepted).  Frees its device tables. */
+int destroy_geometry(pl_geometry* geom);
+
+/*
+ * Describe a geometry.  Any of the host arrays may be NULL; otherwise they
+ * receive: tx_xy_host / rx_xy_host [n_channels][2] transmit / receive phase
+ * centres (m), z_scan_host [n_scan] (m), freq_host [n_freq] (Hz),
+ * chord_ends_host [n_chords][2][2] chord start/end points (m).
+ */
+int geometry_info(const pl_geometry* geom, pl_geometry_info* info, double* tx_xy_host,
+                  double* rx_xy_host, double* z_scan_host, double* freq_host,
+                  double* chord_ends_host);
+
+/* ------------------------------------------------------------ image grid */
+/* Pixel (ix, iy) is centred at (x0 + ix*dx, y0 + iy*dy); nx, ny >= 1; dx, dy > 0. */
+typedef struct pl_image_grid {
+    int32_t nx;
+    int32_t ny;
+    double x0;
+    double y0;
+    double dx;
+    double dy;
+} pl_image_grid;
+
+/*
+ * Sampling criteria of Sec. II-C for this array imaging this pixel grid:
+ * element spacing against eq. (21) (half of it for monostatic arrays) with D
+ * the grid's horizontal extent and R_0 the distance from the middle section
+ * to the grid centre, and the scan step against eq. (22) with Theta_z the
+ * angle the scan length subtends from the grid centre.  *warnings receives
+ * PL_WARN_* bits.
+ */
+int check_sampling(const pl_geometry* geom, const pl_image_grid* grid, uint32_t* warnings);
+
+/* ------------------------------------------------------------ simulation */
+/*
+ * Point-scatterer echoes, eq. (1) (monostatic) and eq. (10) (multistatic):
+ *   s[c][m][f] = sum_p sigma_p exp(-j k_f (R_T + R_R)),  k_f = 2 pi f / c,
+ * with R_T, R_R the 3-D distances from the channel's Tx and Rx at height z'_m
+ * to scatterer p (R_T = R_R for monostatic channels).  No amplitude decay or
+ * antenna pattern, as in the paper.
+ *   xyz_dev   [n_scat][3] float64 positions (m), device.
+ *   refl_dev  [n_scat][2] float64 complex reflectivities (re, im), device.
+ *   echo_dev  [n_channels][n_scan][n_freq] complex64 output, device.
+ * Phases are formed in float64 and range-reduced before float32 sin/cos.
+ * Errors: PL_EINVAL (null pointer, n_scat < 0), PL_EDEVICE.
+ */
+int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev,
+                  const double* refl_dev, float* echo_dev, hipStream_t stream);
+
+/* ------------------------------------------------- hybrid reconstruction */
+#define PL_PREC_FP32 0 /* range compression by FP32 NUFFT on the vector ALUs      */
+#define PL_PREC_BF16 1 /* range compression as a BF16 MFMA contraction, split     */
+                       /* hi+lo operands, FP32 accumulation                       */
+#define PL_PREC_FP16 2 /* same with FP16 operands (hi+lo split, scaled)           */
+
+#define PL_INTERP_BSPLINE4 0  /* cubic B-spline; its prefilter is applied per     */
+                              /* frequency before range compression (default)    */
+#define PL_INTERP_LAGRANGE4 1 /* cubic Lagrange on the range samples             */
+#define PL_INTERP_LINEAR 2    /* linear (the simplest "1-D interpolation")       */
+
+/*
+ * Options of the hybrid method.  Zero-initialised fields take the defaults.
+ *   precision     PL_PREC_* (default FP32).
+ *   interp        PL_INTERP_* (default cubic B-spline).
+ *   l_oversample  range-grid oversampling over the Nyquist rate of the
+ *                 baseband range profile (default 8; >= 2).
+ *   nufft_tol     NUFFT tolerance (default 1e-6; 1e-12 .. 1e-2).
+ */
+typedef struct pl_hybrid_opts {
+    int32_t precision;
+    int32_t interp;
+    double l_oversample;
+    double nufft_tol;
+} pl_hybrid_opts;
+
+/* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */
+typedef struct pl_hybrid_plan_info {
+    int32_t n_kz;        /* k_z bins (= n_scan)                                  */
+    int32_t n_l;         /* range samples per (channel, k_z)                     */
+    int32_t n_fine;      /* NUFFT fine-grid length (2 n_l)                       */
+    int32_t kernel_width;/* NUFFT spreading-kernel width W                       */
+    int32_t n_blocks;    /* k_z blocks sharing one reference wavenumber          */
+    int32_t block;       /* k_z bins per block                                   */
+    int32_t window;      /* range samples staged per pixel tile and channel      */
+    int32_t tile_x;      /* back-projection pixel tile                           */
+    int32_t tile_y;
+    int32_t reserved;
+    double du;           /* range-grid step (m of rho_T + rho_R)                 */
+    double beta;         /* exponential-of-semicircle kernel shape               */
+    size_t workspace_bytes;
+} pl_hybrid_plan_info;
+
+/*
+ * Plan sizes for a hybrid reconstruction (host-only).  k_ref_host, if not
+ * NULL, receives n_blocks reference wavenumbers (rad/m, for the range
+ * rho_T + rho_R; monostatic ranges are 2 rho).  Errors: PL_EINVAL,
+ * PL_EUNSUPPORTED (grid or problem beyond the supported sizes).
+ */
+int hybrid_plan_info(const pl_geometry* geom, const pl_image_grid* grid,
+                     const pl_hybrid_opts* opts, pl_hybrid_plan_info* info,
+                     double* k_ref_host);
+
+/* Workspace bytes reconstruct_hybrid needs (host-only). */
+int hybrid_workspace_bytes(const pl_geometry* geom, const pl_image_grid* grid,
+                           const pl_hybrid_opts* opts, size_t* bytes);
+
+/*
+ * The hybrid reconstruction of Sec. II (eqs. 2-9; multistatic 12-19):
+ *   1. S = FFT over the scan axis of s (eq. 2/12);
+ *   2. per channel and k_z, range compression q(l) = sum_f k_f S e^{j k'_f l}
+ *      on a uniform range grid by a type-1 NUFFT (eq. 8a/19a);
+ *   3. per k_z, interpolation of q at each pixel's range l_c(p) = rho
+ *      (mono) or rho_T + rho_R (multi), carrier e^{j k_ref l}, and the sum
+ *      over channels (eq. 8b/19b);
+ *   4. inverse FFT over k_z (eq. 9).
+ * The result approximates the exact double sum
+ *   G(k_z, p) = sum_c sum_f k_f S[c,k_z,f] exp(j k_rho(f,k_z) l_c(p)),
+ *   g = IFFT_kz G,
+ * to the tolerance the options set.
+ *   echo_dev   [n_channels][n_scan][n_freq] complex64, read only.
+ *   image_dev  [n_scan][ny][nx] complex64 output; must not alias echo or ws.
+ *   ws         device workspace of at least hybrid_workspace_bytes bytes,
+ *              256-byte aligned; its contents are scratch.
+ * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.
+ */
+int reconstruct_hybrid(const pl_geometry* geom, const pl_image_grid* grid,
+                       const pl_hybrid_opts* opts, const float* echo_dev, float* image_dev,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * reconstruct_hybrid with stage timing for profilers: records
+ * stage_events[i] on the stream before stage i and stage_events[5] after the
+ * last stage.  Stages: 0 plan tables, 1 scan FFT, 2 range compression,
+ * 3 back-projection, 4 k_z inverse FFT.  Events are created and owned by the
+ * caller (hipEventCreate); NULL entries are skipped; stage_events itself may
+ * be NULL.  Nothing is synchronised.  Same errors as reconstruct_hybrid.
+ */
+int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid,
+                              const pl_hybrid_opts* opts, const float* echo_dev,
+                              float* image_dev, void* ws, size_t ws_bytes,
+                              hipEvent_t* stage_events, hipStream_t stream);
+
+/* ------------------------------------------------- the hybrid steps alone */
+/*
+ * The four steps of reconstruct_hybrid as separate calls, for inspection and
+ * step-level checks.  They use the same plan; buffers are device memory:
+ *   scan_fft:        echo [c][m][f] -> spec [c][kz][f]        (eq. 2/12)
+ *   range_compress:  spec [c][kz][f] -> q [c][kz][n_l]        (eq. 8a/19a)
+ *       q[c][kz][i] approximates sum_f w_f k_f S e^{j k'_f l_i} with
+ *       k' = k_rho - k_ref(block of kz), l_i = l_lo[c] + i du, where w_f is
+ *       1 except for PL_INTERP_BSPLINE4, where it is the B-spline prefilter
+ *       1 / sinc^4(k'_f du / 2) (q then holds spline coefficients).
+ *   backproject:     q -> G [p][kz] with p = iy * nx + ix      (eq. 8b/19b)
+ *   kz_ifft:         G [p][kz] -> image [z][y][x]              (eq. 9)
+ * range_lo_host, if not NULL, receives l_lo[c] (n_channels doubles).
+ * ws must be at least hybrid_workspace_bytes; range_compress and backproject
+ * use it for their tables.
+ */
+int scan_fft(const pl_geometry* geom, const float* echo_dev, float* spec_dev, hipStream_t stream);
+int range_compress(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                   const float* spec_dev, float* q_dev, double* range_lo_host, void* ws,
+                   size_t ws_bytes, hipStream_t stream);
+int backproject(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                const float* q_dev, float* spectrum_dev, void* ws, size_t ws_bytes,
+                hipStream_t stream);
+int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spectrum_dev,
+            float* image_dev, hipStream_t stream);
+
+/* -------------------------------------------------------- back-projection */
+/*
+ * Brute-force back-projection (the paper's comparison method; its formula is
+ * not written in the paper; the matched filter of eqs. 1/10 with weight k_f):
+ *   g(x,y,z_m) = sum_c sum_m' sum_f k_f s[c,m',f] exp(+j k_f (R_T + R_R)),
+ * over all channels and scan positions, for image planes z_m with
+ * m in [iz0, iz0 + nz).  image_dev is [nz][ny][nx] complex64.
+ * ws: at least bp_workspace_bytes (the k_f-weighted echo).
+ * Errors: PL_EINVAL, PL_EWORKSPACE, PL_EDEVICE.
+ */
+int bp_workspace_bytes(const pl_geometry* geom, size_t* bytes);
+int reconstruct_bp(const pl_geometry* geom, const pl_image_grid* grid, int32_t iz0, int32_t nz,
+                   const float* echo_dev, float* image_dev, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLYRECON_H */

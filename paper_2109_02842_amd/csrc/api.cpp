@@ -1,0 +1,236 @@
+// C-ABI entry points of the polyrecon library: argument checks, planning,
+// and the launch sequence of each call.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace pl {
+namespace {
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+int prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws, size_t ws_bytes,
+            HybridPlan* p, DeviceTables* dt, const char* what) {
+    int rc = make_plan(g, grid, opts, p);
+    if (rc) return rc;
+    if (!ws) return fail(PL_EWORKSPACE, "%s: null workspace", what);
+    if (!aligned256(ws)) return fail(PL_EWORKSPACE, "%s: workspace must be 256-byte aligned", what);
+    if (ws_bytes < p->total)
+        return fail(PL_EWORKSPACE, "%s: workspace of %zu bytes, %zu needed", what, ws_bytes, p->total);
+    return g->device_tables(dt);
+}
+
+// Twiddle table exp(-2 pi i t / n) for the standalone transform calls, kept
+// per (device, n) for the life of the process (a few KiB each).
+int scan_twiddles(int n, hipStream_t stream, float2** out) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, float2*> tables;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PL_EDEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, n);
+    auto it = tables.find(key);
+    if (it != tables.end()) {
+        *out = it->second;
+        return PL_OK;
+    }
+    float2* tw = nullptr;
+    if (hipMalloc(&tw, sizeof(float2) * n) != hipSuccess) return fail(PL_EDEVICE, "twiddle allocation failed");
+    int rc = launch_twiddles(tw, n, stream);
+    if (rc == PL_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(PL_EDEVICE, "twiddle table failed");
+    if (rc) {
+        (void)hipFree(tw);
+        return rc;
+    }
+    tables[key] = tw;
+    *out = tw;
+    return PL_OK;
+}
+
+}  // namespace
+}  // namespace pl
+
+extern "C" {
+
+int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                     pl_hybrid_plan_info* info, double* k_ref_host) {
+    using namespace pl;
+    clear_error();
+    if (!info) return fail(PL_EINVAL, "hybrid_plan_info: null info");
+    HybridPlan p;
+    const int rc = make_plan(g, grid, opts, &p);
+    if (rc) return rc;
+    info->n_kz = p.n_z;
+    info->n_l = p.n_l;
+    info->n_fine = p.n_fine;
+    info->kernel_width = p.W;
+    info->n_blocks = p.n_blocks;
+    info->block = kBlock;
+    info->window = p.window;
+    info->tile_x = p.tile_x;
+    info->tile_y = p.tile_y;
+    info->reserved = 0;
+    info->du = p.du;
+    info->beta = p.beta;
+    info->workspace_bytes = p.total;
+    if (k_ref_host) std::memcpy(k_ref_host, p.kref, sizeof(double) * p.n_blocks);
+    return PL_OK;
+}
+
+int hybrid_workspace_bytes(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                           size_t* bytes) {
+    using namespace pl;
+    clear_error();
+    if (!bytes) return fail(PL_EINVAL, "hybrid_workspace_bytes: null output");
+    HybridPlan p;
+    const int rc = make_plan(g, grid, opts, &p);
+    if (rc) return rc;
+    *bytes = p.total;
+    return PL_OK;
+}
+
+int simulate_echo(const pl_geometry* g, int32_t n_scat, const double* xyz, const double* refl, float* echo,
+                  hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!g || !echo) return fail(PL_EINVAL, "simulate_echo: null geometry or echo");
+    if (n_scat < 0) return fail(PL_EINVAL, "simulate_echo: n_scat < 0");
+    if (n_scat > 0 && (!xyz || !refl)) return fail(PL_EINVAL, "simulate_echo: null scatterer arrays");
+    DeviceTables dt;
+    int rc = g->device_tables(&dt);
+    if (rc) return rc;
+    return launch_simulate(g, dt, n_scat, xyz, refl, reinterpret_cast<float2*>(echo), stream);
+}
+
+int scan_fft(const pl_geometry* g, const float* echo, float* spec, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!g || !echo || !spec) return fail(PL_EINVAL, "scan_fft: null pointer");
+    Radices rad;
+    if (!factor_radices(g->n_scan, &rad))
+        return fail(PL_EUNSUPPORTED, "scan_fft: n_scan = %d is not a product of 2, 3 and 5", g->n_scan);
+    float2* tw = nullptr;
+    const int rc = scan_twiddles(g->n_scan, stream, &tw);
+    if (rc) return rc;
+    return launch_scan_fft(g, reinterpret_cast<const float2*>(echo), reinterpret_cast<float2*>(spec), tw, rad, stream);
+}
+
+int range_compress(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* spec,
+                   float* q, double* range_lo_host, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!spec || !q) return fail(PL_EINVAL, "range_compress: null pointer");
+    HybridPlan p;
+    DeviceTables dt;
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "range_compress");
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
+    rc = p.precision == PL_PREC_FP32
+             ? launch_range_compress_fp32(p, reinterpret_cast<const float2*>(spec), w, reinterpret_cast<float2*>(q), stream)
+             : launch_range_compress_mfma(p, reinterpret_cast<const float2*>(spec), w, reinterpret_cast<float2*>(q), stream);
+    if (rc) return rc;
+    if (range_lo_host) {
+        if (hipMemcpyAsync(range_lo_host, w + p.off_llo, sizeof(double) * p.n_ch, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return fail(PL_EDEVICE, "range_compress: copying range origins failed");
+    }
+    return PL_OK;
+}
+
+int backproject(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* q,
+                float* spectrum, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!q || !spectrum) return fail(PL_EINVAL, "backproject: null pointer");
+    HybridPlan p;
+    DeviceTables dt;
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "backproject");
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
+    return launch_backproject(p, dt, reinterpret_cast<const float2*>(q), w, reinterpret_cast<float2*>(spectrum), stream);
+}
+
+int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectrum, float* image, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!g || !grid || !spectrum || !image) return fail(PL_EINVAL, "kz_ifft: null pointer");
+    if (grid->nx < 1 || grid->ny < 1) return fail(PL_EINVAL, "kz_ifft: bad grid");
+    HybridPlan p;
+    p.n_z = g->n_scan;
+    p.nx = grid->nx;
+    p.ny = grid->ny;
+    if (!factor_radices(p.n_z, &p.scan_rad)) return fail(PL_EUNSUPPORTED, "kz_ifft: n_scan not 2,3,5-smooth");
+    float2* tw = nullptr;
+    const int rc = scan_twiddles(g->n_scan, stream, &tw);
+    if (rc) return rc;
+    return launch_kz_ifft(p, reinterpret_cast<const float2*>(spectrum), reinterpret_cast<float2*>(image), tw, stream);
+}
+
+int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                              const float* echo, float* image, void* ws, size_t ws_bytes, hipEvent_t* ev,
+                              hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!echo || !image) return fail(PL_EINVAL, "reconstruct_hybrid: null echo or image");
+    HybridPlan p;
+    DeviceTables dt;
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "reconstruct_hybrid");
+    if (rc) return rc;
+    auto mark = [&](int i) -> int {
+        if (ev && ev[i] && hipEventRecord(ev[i], stream) != hipSuccess)
+            return fail(PL_EDEVICE, "reconstruct_hybrid: hipEventRecord failed");
+        return PL_OK;
+    };
+    char* w = static_cast<char*>(ws);
+    float2* spec = reinterpret_cast<float2*>(w + p.off_spec);
+    float2* q = reinterpret_cast<float2*>(w + p.off_q);
+    float2* G = reinterpret_cast<float2*>(w + p.off_G);
+    const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
+    if ((rc = mark(0)) || (rc = launch_plan_tables(p, dt, w, stream))) return rc;
+    if ((rc = mark(1)) ||
+        (rc = launch_scan_fft(g, reinterpret_cast<const float2*>(echo), spec, tw_scan, p.scan_rad, stream)))
+        return rc;
+    if ((rc = mark(2))) return rc;
+    rc = p.precision == PL_PREC_FP32 ? launch_range_compress_fp32(p, spec, w, q, stream)
+                                     : launch_range_compress_mfma(p, spec, w, q, stream);
+    if (rc) return rc;
+    if ((rc = mark(3)) || (rc = launch_backproject(p, dt, q, w, G, stream))) return rc;
+    if ((rc = mark(4)) || (rc = launch_kz_ifft(p, G, reinterpret_cast<float2*>(image), tw_scan, stream))) return rc;
+    return mark(5);
+}
+
+int reconstruct_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
+                       float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return reconstruct_hybrid_events(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream);
+}
+
+int bp_workspace_bytes(const pl_geometry* g, size_t* bytes) {
+    pl::clear_error();
+    if (!g || !bytes) return pl::fail(PL_EINVAL, "bp_workspace_bytes: null pointer");
+    *bytes = static_cast<size_t>(g->n_ch) * g->n_scan * g->n_freq * 8;
+    return PL_OK;
+}
+
+int reconstruct_bp(const pl_geometry* g, const pl_image_grid* grid, int32_t iz0, int32_t nz, const float* echo,
+                   float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!g || !grid || !echo || !image) return fail(PL_EINVAL, "reconstruct_bp: null pointer");
+    if (grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0) || !(grid->dy > 0))
+        return fail(PL_EINVAL, "reconstruct_bp: bad grid");
+    if (iz0 < 0 || nz < 1 || iz0 + nz > g->n_scan)
+        return fail(PL_EINVAL, "reconstruct_bp: planes [%d, %d) outside [0, %d)", iz0, iz0 + nz, g->n_scan);
+    const size_t need = static_cast<size_t>(g->n_ch) * g->n_scan * g->n_freq * 8;
+    if (!ws || ws_bytes < need) return fail(PL_EWORKSPACE, "reconstruct_bp: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    DeviceTables dt;
+    int rc = g->device_tables(&dt);
+    if (rc) return rc;
+    return launch_bp(g, dt, grid, iz0, nz, reinterpret_cast<const float2*>(echo), static_cast<float2*>(ws),
+                     reinterpret_cast<float2*>(image), stream);
+}
+
+}  // extern "C"

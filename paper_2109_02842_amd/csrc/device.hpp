@@ -1,0 +1,161 @@
+// Device helpers shared by the polyrecon kernels: complex arithmetic, phasors
+// with float64 range reduction, and a mixed-radix Stockham FFT in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace pl {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by +i (sgn = +1) or -i (sgn = -1)
+__device__ __forceinline__ float2 cmul_i(float2 a, int sgn) {
+    return sgn > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// exp(j 2 pi rev): the revolution count is reduced to [-1/2, 1/2] in float64
+// before the float32 evaluation, so phases of thousands of radians keep full
+// float32 accuracy.
+__device__ __forceinline__ float2 cis_rev(double rev) {
+    const double r = rev - rint(rev);
+    float s, c;
+    sincospif(static_cast<float>(2.0 * r), &s, &c);
+    return make_float2(c, s);
+}
+
+// exp(j phase) for a float64 phase in radians.
+__device__ __forceinline__ float2 cis(double phase) { return cis_rev(phase * (0.5 / kPi)); }
+
+// ------------------------------------------------------------ Stockham FFT
+// One radix-R butterfly on registers: X_r = sum_q a_q exp(sgn 2 pi i q r / R).
+template <int R>
+__device__ __forceinline__ void dft_small(float2* a, int sgn);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(float2* a, int) {
+    const float2 t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(float2* a, int sgn) {
+    const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    const float2 t2 = cadd(a[1], a[3]), t3 = cmul_i(csub(a[1], a[3]), sgn);
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<8>(float2* a, int sgn) {
+    // split into even and odd halves, two radix-4 transforms, then combine
+    float2 e[4] = {a[0], a[2], a[4], a[6]};
+    float2 o[4] = {a[1], a[3], a[5], a[7]};
+    dft_small<4>(e, sgn);
+    dft_small<4>(o, sgn);
+    const float h = 0.70710678118654752f;
+    // twiddles exp(sgn 2 pi i q / 8), q = 0..3
+    const float2 w1 = make_float2(h, sgn * h);
+    o[1] = cmul(o[1], w1);
+    o[2] = cmul_i(o[2], sgn);
+    o[3] = cmul(o[3], make_float2(-h, sgn * h));
+    for (int q = 0; q < 4; ++q) {
+        a[q] = cadd(e[q], o[q]);
+        a[q + 4] = csub(e[q], o[q]);
+    }
+}
+
+template <>
+__device__ __forceinline__ void dft_small<3>(float2* a, int sgn) {
+    const float c = -0.5f, s = 0.86602540378443865f * sgn;
+    const float2 t = cadd(a[1], a[2]);
+    const float2 u = csub(a[1], a[2]);
+    const float2 m = make_float2(a[0].x + c * t.x, a[0].y + c * t.y);
+    const float2 v = make_float2(-s * u.y, s * u.x);  // i s u
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(m, v);
+    a[2] = csub(m, v);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<5>(float2* a, int sgn) {
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = 0.95105651629515357f * sgn, s2 = 0.58778525229247313f * sgn;
+    const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const float2 u1 = csub(a[1], a[4]), u2 = csub(a[2], a[3]);
+    const float2 m1 = make_float2(a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 m2 = make_float2(a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y);
+    // i (s1 u1 + s2 u2) and i (s2 u1 - s1 u2)
+    const float2 v1 = make_float2(-(s1 * u1.y + s2 * u2.y), s1 * u1.x + s2 * u2.x);
+    const float2 v2 = make_float2(-(s2 * u1.y - s1 * u2.y), s2 * u1.x - s1 * u2.x);
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(m1, v1);
+    a[4] = csub(m1, v1);
+    a[2] = cadd(m2, v2);
+    a[3] = csub(m2, v2);
+}
+
+// One Stockham stage of radix R over `ntr` transforms of length n stored at
+// src[t * ld + i]; writes dst.  tw[j] = exp(-2 pi i j / n).  Ns is the product
+// of the radices of the previous stages.
+template <int R>
+__device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, float2* __restrict__ dst,
+                                               int n, int ld, int ntr, int Ns,
+                                               const float2* __restrict__ tw, int sgn, int tid,
+                                               int nthreads) {
+    const int nb = n / R;
+    const int tstep = n / (Ns * R);
+    const int total = nb * ntr;
+    for (int b = tid; b < total; b += nthreads) {
+        const int t = b / nb;
+        const int j = b - t * nb;
+        const int k = j % Ns;
+        const float2* s = src + t * ld;
+        float2 a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = s[j + r * nb];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            float2 w = tw[r * k * tstep];
+            if (sgn > 0) w.y = -w.y;
+            a[r] = cmul(a[r], w);
+        }
+        dft_small<R>(a, sgn);
+        float2* d = dst + t * ld + (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r * Ns] = a[r];
+    }
+}
+
+// Full transform in LDS; returns the buffer holding the result (a or b).
+// Barriers are issued by every thread of the block.
+__device__ inline float2* lds_fft(float2* a, float2* b, int n, int ld, int ntr, const Radices& rad,
+                                  const float2* __restrict__ tw, int sgn, int tid, int nthreads) {
+    int Ns = 1;
+    for (int st = 0; st < rad.count; ++st) {
+        const int R = rad.r[st];
+        switch (R) {
+            case 8: stockham_stage<8>(a, b, n, ld, ntr, Ns, tw, sgn, tid, nthreads); break;
+            case 4: stockham_stage<4>(a, b, n, ld, ntr, Ns, tw, sgn, tid, nthreads); break;
+            case 2: stockham_stage<2>(a, b, n, ld, ntr, Ns, tw, sgn, tid, nthreads); break;
+            case 3: stockham_stage<3>(a, b, n, ld, ntr, Ns, tw, sgn, tid, nthreads); break;
+            default: stockham_stage<5>(a, b, n, ld, ntr, Ns, tw, sgn, tid, nthreads); break;
+        }
+        __syncthreads();
+        float2* t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+}  // namespace pl

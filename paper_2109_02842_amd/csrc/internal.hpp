@@ -1,0 +1,116 @@
+// Internal declarations of the polyrecon library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/polyrecon.h"
+
+namespace pl {
+
+constexpr double kSpeedOfLight = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kBlock = 64;          // k_z bins per block: one per lane of a wavefront
+constexpr int kMaxScan = 4096;
+constexpr int kMaxBlocks = kMaxScan / kBlock;
+constexpr int kMaxFreq = 1024;
+constexpr int kMaxFine = 4096;      // NUFFT fine grid held twice in LDS (64 KiB)
+constexpr int kMaxGL = 64;          // quadrature nodes for the kernel transform
+constexpr int kMaxRadices = 16;
+
+// ---------------------------------------------------------------- errors
+int fail(int code, const char* fmt, ...);
+void clear_error();
+int check_launch(const char* what);
+
+// ------------------------------------------------------- device geometry
+struct DeviceTables {
+    double* chan = nullptr;  // [n_ch][4]: x_T, y_T, x_R, y_R
+    double* k = nullptr;     // [n_freq] wavenumbers
+};
+
+// Radix plan of a transform length (radices in {8, 4, 2, 3, 5}).
+struct Radices {
+    int n = 0;
+    int count = 0;
+    int r[kMaxRadices] = {};
+};
+bool factor_radices(int n, Radices* out);
+bool is_fft_friendly(int n);
+
+}  // namespace pl
+
+struct pl_geometry {
+    int mode = PL_MONO;
+    int n_chords = 0, n_elem = 0, n_tx = 0, n_scan = 0, n_freq = 0, n_ch = 0;
+    double radius = 0, arc_center = 0, spacing = 0, scan_step = 0, scan_z0 = 0;
+    double f_start = 0, f_stop = 0;
+    std::vector<double> tx_off;          // chord-local Tx offsets (multi)
+    std::vector<double> tx, rx;          // [n_ch][2]
+    std::vector<double> z, f, k;         // scan heights, frequencies, wavenumbers
+    std::vector<double> ends;            // [n_chords][2][2]
+    mutable std::mutex mu;
+    mutable std::map<int, pl::DeviceTables> dev;
+
+    // Device tables for the current device (uploaded on first use).
+    int device_tables(pl::DeviceTables* out) const;
+    ~pl_geometry();
+};
+
+namespace pl {
+
+// Host-side plan of a hybrid reconstruction: every size and scalar the
+// kernels need, and the workspace layout.
+struct HybridPlan {
+    int mode = 0, n_ch = 0, n_z = 0, n_f = 0;
+    double scan_step = 0;
+    int nx = 0, ny = 0;
+    double x0 = 0, y0 = 0, dx = 0, dy = 0;
+    int precision = PL_PREC_FP32, interp = PL_INTERP_BSPLINE4;
+    double sigma_l = 8.0, tol = 1e-6;
+    // range grid and NUFFT
+    int n_l = 0, n_fine = 0, W = 0;
+    double du = 0, h = 0, beta = 0;
+    int n_blocks = 0;
+    double kref[kMaxBlocks] = {};
+    Radices scan_rad, fine_rad;
+    int n_gl = 0;
+    double gl_x[kMaxGL] = {}, gl_w[kMaxGL] = {};
+    // back-projection tiling
+    int tile_x = 8, tile_y = 8, tiles_x = 0, tiles_y = 0, window = 0, window_pad = 0;
+    // interpolation weights w_k(t) = sum_j coef[k][j] t^j, taps at floor(u)-1+k
+    float coef[4][4] = {};
+    // workspace layout (byte offsets, 256-aligned)
+    size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_tw_scan = 0, off_tw_fine = 0;
+    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, total = 0;
+};
+
+int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+              HybridPlan* p);
+
+// ---------------------------------------------------------- launchers
+int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
+int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const float2* tw,
+                    const Radices& rad, hipStream_t s);
+int launch_twiddles(float2* tw, int n, hipStream_t s);
+int launch_range_compress_fp32(const HybridPlan& p, const float2* spec, char* ws, float2* q,
+                               hipStream_t s);
+int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q,
+                               hipStream_t s);
+int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws,
+                       float2* G, hipStream_t s);
+int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw,
+                   hipStream_t s);
+int launch_simulate(const pl_geometry* g, const DeviceTables& dt, int n_scat, const double* xyz,
+                    const double* refl, float2* echo, hipStream_t s);
+int launch_bp(const pl_geometry* g, const DeviceTables& dt, const pl_image_grid* grid, int iz0,
+              int nz, const float2* echo, float2* weighted, float2* image, hipStream_t s);
+
+}  // namespace pl

@@ -1,0 +1,227 @@
+// Plan tables, the batched FFTs over the scan axis (eq. 2/12) and over k_z
+// (eq. 9), and twiddle tables.
+#include "device.hpp"
+
+namespace pl {
+namespace {
+
+struct PlanTablesArgs {
+    int n_ch, n_z, n_f, n_l, n_fine, interp, n_gl, pad_;
+    double du, h, beta, scan_step;
+    double gx0, gx1, gy0, gy1;
+    double kref[kMaxBlocks];
+    double glx[kMaxGL];
+    double glw[kMaxGL];
+};
+
+__device__ double dist_to_rect(double px, double py, double x0, double x1, double y0, double y1) {
+    const double cx = fmin(fmax(px, x0), x1), cy = fmin(fmax(py, y0), y1);
+    return hypot(px - cx, py - cy);
+}
+
+// Fills the per-call tables of the hybrid plan:
+//   llo[c]       start of channel c's range grid (lowest range over the pixel
+//                rectangle minus two steps)
+//   tw_scan[t]   exp(-2 pi i t / n_z);  tw_fine[t]  exp(-2 pi i t / n_fine)
+//   deap[i]      1 / (h * FT of the spreading kernel) at output mode i - n_l/2
+//   kp[kz][f]    k' = k_rho - k_ref(block), k_rho = sqrt(k^2 - k_z^2/4) (0 if evanescent)
+//   wk[kz][f]    k_f (weight of "k dk") times the B-spline prefilter, 0 if evanescent
+__global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ chan,
+                                   const double* __restrict__ k, double* __restrict__ llo,
+                                   float2* __restrict__ tw_scan, float2* __restrict__ tw_fine,
+                                   float* __restrict__ deap, double* __restrict__ kp,
+                                   float* __restrict__ wk) {
+    const long long n0 = a.n_ch, n1 = n0 + a.n_z, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
+    const long long total = n3 + static_cast<long long>(a.n_z) * a.n_f;
+    for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < total;
+         idx += static_cast<long long>(gridDim.x) * blockDim.x) {
+        if (idx < n0) {
+            const int c = static_cast<int>(idx);
+            const double lmin = dist_to_rect(chan[4 * c], chan[4 * c + 1], a.gx0, a.gx1, a.gy0, a.gy1) +
+                                dist_to_rect(chan[4 * c + 2], chan[4 * c + 3], a.gx0, a.gx1, a.gy0, a.gy1);
+            llo[c] = lmin - 2.0 * a.du;
+        } else if (idx < n1) {
+            const int t = static_cast<int>(idx - n0);
+            double s, c;
+            sincospi(-2.0 * t / a.n_z, &s, &c);
+            tw_scan[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
+        } else if (idx < n2) {
+            const int t = static_cast<int>(idx - n1);
+            double s, c;
+            sincospi(-2.0 * t / a.n_fine, &s, &c);
+            tw_fine[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
+        } else if (idx < n3) {
+            const int i = static_cast<int>(idx - n2);
+            const double xi = 2.0 * kPi * a.h * (i - a.n_l / 2) / a.n_fine;
+            double ft = 0.0;
+            for (int q = 0; q < a.n_gl; ++q) {
+                const double z = a.glx[q];
+                ft += a.glw[q] * exp(a.beta * (sqrt(1.0 - z * z) - 1.0)) * cos(xi * z);
+            }
+            deap[i] = static_cast<float>(1.0 / (a.h * ft));
+        } else {
+            const long long e = idx - n3;
+            const int kap = static_cast<int>(e / a.n_f), f = static_cast<int>(e % a.n_f);
+            const int sk = kap < (a.n_z + 1) / 2 ? kap : kap - a.n_z;
+            const double kz = 2.0 * kPi * sk / (a.n_z * a.scan_step);
+            const double arg = k[f] * k[f] - 0.25 * kz * kz;
+            const bool valid = arg > 0.0;
+            const double kr = valid ? sqrt(arg) : 0.0;
+            const double kpr = kr - a.kref[kap / kBlock];
+            kp[e] = kpr;
+            double w = valid ? k[f] : 0.0;
+            if (valid && a.interp == PL_INTERP_BSPLINE4) {
+                const double x = 0.5 * kpr * a.du;
+                const double sinc = fabs(x) < 1e-8 ? 1.0 - x * x / 6.0 : sin(x) / x;
+                w /= (sinc * sinc) * (sinc * sinc);
+            }
+            wk[e] = static_cast<float>(w);
+        }
+    }
+}
+
+__global__ void twiddle_kernel(float2* tw, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double s, c;
+    sincospi(-2.0 * t / n, &s, &c);
+    tw[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
+}
+
+struct FftArgs {
+    int n, nbatch, inner, per_wg, ld, sign, n_fast_in, n_fast_out;
+    long long in_so, in_si, in_sn, out_so, out_si, out_sn;
+    float scale;
+    int pad_;
+    Radices rad;
+};
+
+// Batched FFT of length n along a strided axis.  Batch index b splits into
+// (outer o = b / inner, inner s = b % inner); element i of transform b is at
+// in[o*in_so + s*in_si + i*in_sn].  Each block transforms per_wg batches in
+// LDS (two buffers of per_wg * ld complex values).
+__global__ __launch_bounds__(256) void fft_strided_kernel(const float2* __restrict__ in,
+                                                          float2* __restrict__ out,
+                                                          const float2* __restrict__ tw, FftArgs a) {
+    extern __shared__ float2 smem[];
+    float2* A = smem;
+    float2* B = smem + a.per_wg * a.ld;
+    const int b0 = blockIdx.x * a.per_wg;
+    const int nb = min(a.per_wg, a.nbatch - b0);
+    const int total = nb * a.n;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < total; e += blockDim.x) {
+        int t, i;
+        if (a.n_fast_in) {
+            t = e / a.n;
+            i = e - t * a.n;
+        } else {
+            i = e / nb;
+            t = e - i * nb;
+        }
+        const int b = b0 + t;
+        const int o = b / a.inner, s = b - o * a.inner;
+        A[t * a.ld + i] = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+    }
+    __syncthreads();
+    const float2* res = lds_fft(A, B, a.n, a.ld, nb, a.rad, tw, a.sign, tid, blockDim.x);
+    for (int e = tid; e < total; e += blockDim.x) {
+        int t, i;
+        if (a.n_fast_out) {
+            t = e / a.n;
+            i = e - t * a.n;
+        } else {
+            i = e / nb;
+            t = e - i * nb;
+        }
+        const int b = b0 + t;
+        const int o = b / a.inner, s = b - o * a.inner;
+        out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(res[t * a.ld + i], a.scale);
+    }
+}
+
+int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nbatch, int inner,
+            long long in_so, long long in_si, long long in_sn, long long out_so, long long out_si,
+            long long out_sn, int sign, float scale, const Radices& rad, hipStream_t s,
+            const char* what) {
+    FftArgs a{};
+    a.n = n;
+    a.nbatch = static_cast<int>(nbatch);
+    a.inner = inner;
+    a.per_wg = std::max(1, std::min(64, 2048 / n));
+    a.ld = n + 1;
+    a.sign = sign;
+    a.n_fast_in = in_sn == 1;
+    a.n_fast_out = out_sn == 1;
+    a.in_so = in_so;
+    a.in_si = in_si;
+    a.in_sn = in_sn;
+    a.out_so = out_so;
+    a.out_si = out_si;
+    a.out_sn = out_sn;
+    a.scale = scale;
+    a.rad = rad;
+    if (nbatch <= 0) return PL_OK;
+    if (nbatch > (1LL << 31) - 1) return fail(PL_EUNSUPPORTED, "%s: too many transforms", what);
+    const size_t smem = 2ull * a.per_wg * a.ld * sizeof(float2);
+    const long long blocks = (nbatch + a.per_wg - 1) / a.per_wg;
+    hipLaunchKernelGGL(fft_strided_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out,
+                       tw, a);
+    return check_launch(what);
+}
+
+}  // namespace
+
+int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s) {
+    PlanTablesArgs a{};
+    a.n_ch = p.n_ch;
+    a.n_z = p.n_z;
+    a.n_f = p.n_f;
+    a.n_l = p.n_l;
+    a.n_fine = p.n_fine;
+    a.interp = p.interp;
+    a.n_gl = p.n_gl;
+    a.du = p.du;
+    a.h = p.h;
+    a.beta = p.beta;
+    a.gx0 = p.x0;
+    a.gx1 = p.x0 + (p.nx - 1) * p.dx;
+    a.gy0 = p.y0;
+    a.gy1 = p.y0 + (p.ny - 1) * p.dy;
+    for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
+    for (int q = 0; q < kMaxGL; ++q) {
+        a.glx[q] = p.gl_x[q];
+        a.glw[q] = p.gl_w[q];
+    }
+    a.scan_step = p.scan_step;
+    const long long total = static_cast<long long>(p.n_ch) + p.n_z + p.n_fine + p.n_l +
+                            static_cast<long long>(p.n_z) * p.n_f;
+    const int blocks = static_cast<int>(std::min<long long>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(plan_tables_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan, dt.k,
+                       reinterpret_cast<double*>(ws + p.off_llo), reinterpret_cast<float2*>(ws + p.off_tw_scan),
+                       reinterpret_cast<float2*>(ws + p.off_tw_fine), reinterpret_cast<float*>(ws + p.off_deap),
+                       reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk));
+    return check_launch("plan tables");
+}
+
+int launch_twiddles(float2* tw, int n, hipStream_t s) {
+    hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
+    return check_launch("twiddles");
+}
+
+// s[c][m][f] -> S[c][kz][f]: forward transform over m (stride n_f).
+int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const float2* tw,
+                    const Radices& rad, hipStream_t s) {
+    const long long nf = g->n_freq, nz = g->n_scan;
+    return run_fft(echo, spec, tw, g->n_scan, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf,
+                   nz * nf, 1, nf, -1, 1.0f, rad, s, "scan fft");
+}
+
+// G[p][kz] -> g[z][p]: inverse transform over k_z with 1/n_z.
+int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw, hipStream_t s) {
+    const long long npix = static_cast<long long>(p.nx) * p.ny;
+    return run_fft(G, image, tw, p.n_z, npix, 1, p.n_z, 0, 1, 1, 0, npix, +1, 1.0f / p.n_z, p.scan_rad, s,
+                   "kz ifft");
+}
+
+}  // namespace pl

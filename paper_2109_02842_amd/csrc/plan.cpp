@@ -1,0 +1,207 @@
+// Host planning of the hybrid reconstruction: range grid, reference
+// wavenumbers, NUFFT parameters, back-projection tiling, workspace layout.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace pl {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, double* x, double* w) {
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) p0 = 1.0, p1 = z;
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Distance from a point to the axis-aligned rectangle [x0,x1] x [y0,y1].
+double dist_to_rect(double px, double py, double x0, double x1, double y0, double y1) {
+    const double cx = std::min(std::max(px, x0), x1), cy = std::min(std::max(py, y0), y1);
+    return std::hypot(px - cx, py - cy);
+}
+
+}  // namespace
+
+int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+              HybridPlan* out) {
+    if (!g || !grid || !out) return fail(PL_EINVAL, "null geometry, grid or plan");
+    if (grid->nx < 1 || grid->ny < 1 || !(grid->dx > 0) || !(grid->dy > 0) ||
+        !std::isfinite(grid->x0) || !std::isfinite(grid->y0))
+        return fail(PL_EINVAL, "image grid needs nx, ny >= 1 and dx, dy > 0");
+    if (static_cast<long long>(grid->nx) * grid->ny > (1LL << 26))
+        return fail(PL_EUNSUPPORTED, "image grid has more than 2^26 pixels");
+    HybridPlan p;
+    p.mode = g->mode;
+    p.n_ch = g->n_ch;
+    p.n_z = g->n_scan;
+    p.n_f = g->n_freq;
+    p.scan_step = g->scan_step;
+    p.nx = grid->nx;
+    p.ny = grid->ny;
+    p.x0 = grid->x0;
+    p.y0 = grid->y0;
+    p.dx = grid->dx;
+    p.dy = grid->dy;
+    if (opts) {
+        p.precision = opts->precision;
+        p.interp = opts->interp;
+        if (opts->l_oversample != 0) p.sigma_l = opts->l_oversample;
+        if (opts->nufft_tol != 0) p.tol = opts->nufft_tol;
+    }
+    if (p.precision < PL_PREC_FP32 || p.precision > PL_PREC_FP16)
+        return fail(PL_EINVAL, "unknown precision %d", p.precision);
+    if (p.interp < PL_INTERP_BSPLINE4 || p.interp > PL_INTERP_LINEAR)
+        return fail(PL_EINVAL, "unknown interpolation %d", p.interp);
+    if (!(p.sigma_l >= 2.0 && p.sigma_l <= 64.0)) return fail(PL_EINVAL, "l_oversample must be in [2, 64]");
+    if (!(p.tol >= 1e-12 && p.tol <= 1e-2)) return fail(PL_EINVAL, "nufft_tol must be in [1e-12, 1e-2]");
+    if (!factor_radices(p.n_z, &p.scan_rad))
+        return fail(PL_EUNSUPPORTED, "n_scan = %d is not a product of 2, 3 and 5", p.n_z);
+
+    // Dispersion k_rho = sqrt(k^2 - k_z^2 / 4) for the range l = rho_T + rho_R
+    // (eq. 18; the monostatic eq. 5 is the same relation with l = 2 rho).
+    // One reference wavenumber per block of k_z bins: the centre of the band
+    // of k_rho it spans.  The reference cancels exactly between eqs. (8a) and
+    // (8b); only the bandwidth of the range profiles depends on it.
+    p.n_blocks = (p.n_z + kBlock - 1) / kBlock;
+    double half_band = 0.0;
+    for (int b = 0; b < p.n_blocks; ++b) {
+        double lo = 1e300, hi = -1e300;
+        for (int kap = b * kBlock; kap < std::min(p.n_z, (b + 1) * kBlock); ++kap) {
+            const int sk = kap < (p.n_z + 1) / 2 ? kap : kap - p.n_z;
+            const double kz = 2.0 * kPi * sk / (p.n_z * g->scan_step);
+            for (int f = 0; f < p.n_f; ++f) {
+                const double arg = g->k[f] * g->k[f] - 0.25 * kz * kz;
+                if (arg <= 0) continue;
+                const double kr = std::sqrt(arg);
+                lo = std::min(lo, kr);
+                hi = std::max(hi, kr);
+            }
+        }
+        if (hi < lo) {
+            p.kref[b] = 0.0;
+        } else {
+            p.kref[b] = 0.5 * (lo + hi);
+            half_band = std::max(half_band, 0.5 * (hi - lo));
+        }
+    }
+    if (half_band <= 0) half_band = 1.0;  // single frequency, no k_z spread
+    p.du = kPi / (p.sigma_l * half_band);
+
+    // Range window of every channel over the pixel-centre rectangle.
+    const double gx1 = grid->x0 + (grid->nx - 1) * grid->dx, gy1 = grid->y0 + (grid->ny - 1) * grid->dy;
+    double span = 0.0;
+    for (int c = 0; c < p.n_ch; ++c) {
+        const double tx = g->tx[2 * c], ty = g->tx[2 * c + 1], rx = g->rx[2 * c], ry = g->rx[2 * c + 1];
+        const double lmin = dist_to_rect(tx, ty, grid->x0, gx1, grid->y0, gy1) +
+                            dist_to_rect(rx, ry, grid->x0, gx1, grid->y0, gy1);
+        double lmax = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            const double x = (i & 1) ? gx1 : grid->x0, y = (i & 2) ? gy1 : grid->y0;
+            lmax = std::max(lmax, std::hypot(x - tx, y - ty) + std::hypot(x - rx, y - ry));
+        }
+        span = std::max(span, lmax - lmin);
+    }
+
+    // Back-projection tile: the staged range window must hold every tap of
+    // the tile's pixels.  |l(p) - l(centre)| <= 2 * half-diagonal.
+    // Prefer the largest tile whose window fits 128 samples and whose LDS
+    // (window starts + two staged windows of 64 rows) stays within 64 KiB.
+    const int tiles[3][2] = {{8, 8}, {4, 4}, {2, 2}};
+    p.window = 0;
+    for (int t = 0; t < 3; ++t) {
+        const double rt = 0.5 * std::hypot((tiles[t][0] - 1) * grid->dx, (tiles[t][1] - 1) * grid->dy);
+        const int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
+        const size_t lds = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * 64 * (wl | 1) * 8;
+        if ((wl <= 128 && lds <= 65536) || t == 2) {
+            p.tile_x = tiles[t][0];
+            p.tile_y = tiles[t][1];
+            p.window = wl;
+            break;
+        }
+    }
+    if (p.window > 128)
+        return fail(PL_EUNSUPPORTED, "pixels are too coarse for the range grid (window %d > 128)", p.window);
+    p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes
+    p.tiles_x = (grid->nx + p.tile_x - 1) / p.tile_x;
+    p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
+
+    int nl = static_cast<int>(std::ceil(span / p.du)) + 8;
+    nl = std::max(nl, p.window + 2);
+    nl += nl & 1;
+    while (!is_fft_friendly(2 * nl)) nl += 2;
+    p.n_l = nl;
+    p.n_fine = 2 * nl;
+    if (p.n_fine > kMaxFine)
+        return fail(PL_EUNSUPPORTED, "range grid of %d samples exceeds %d (lower l_oversample)", nl, kMaxFine / 2);
+    factor_radices(p.n_fine, &p.fine_rad);
+
+    // Exponential-of-semicircle kernel (Barnett, Magland, af Klinteberg 2019)
+    // for a 2x oversampled fine grid: width W = ceil(log10(1/tol)) + 1,
+    // shape beta = 2.30 W.
+    p.W = std::max(2, static_cast<int>(std::ceil(std::log10(1.0 / p.tol))) + 1);
+    p.W = std::min(p.W, 16);
+    p.h = 0.5 * p.W;
+    p.beta = 2.30 * p.W;
+    if (p.n_fine / p.sigma_l + 2 * p.W + 2 >= p.n_fine) return fail(PL_EUNSUPPORTED, "fine grid too short");
+    p.n_gl = std::min(kMaxGL, 4 * p.W + 16);
+    gauss_legendre(p.n_gl, p.gl_x, p.gl_w);
+
+    // interpolation weights as cubic polynomials in t = u - floor(u), taps at
+    // floor(u) - 1 .. floor(u) + 2
+    static const float bsp[4][4] = {{1.f / 6, -0.5f, 0.5f, -1.f / 6},
+                                    {4.f / 6, 0.f, -1.f, 0.5f},
+                                    {1.f / 6, 0.5f, 0.5f, -0.5f},
+                                    {0.f, 0.f, 0.f, 1.f / 6}};
+    static const float lag[4][4] = {{0.f, -1.f / 3, 0.5f, -1.f / 6},
+                                    {1.f, -0.5f, -1.f, 0.5f},
+                                    {0.f, 1.f, 0.5f, -0.5f},
+                                    {0.f, -1.f / 6, 0.f, 1.f / 6}};
+    static const float lin[4][4] = {{0.f, 0.f, 0.f, 0.f}, {1.f, -1.f, 0.f, 0.f}, {0.f, 1.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    const float(*src)[4] = p.interp == PL_INTERP_BSPLINE4 ? bsp : (p.interp == PL_INTERP_LAGRANGE4 ? lag : lin);
+    std::memcpy(p.coef, src, sizeof(p.coef));
+
+    // workspace layout
+    const size_t nch = p.n_ch, nz = p.n_z, nf = p.n_f, npix = static_cast<size_t>(p.nx) * p.ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    p.off_spec = take(nch * nz * nf * 8);
+    p.off_q = take(nch * nz * static_cast<size_t>(p.n_l) * 8);
+    p.off_G = take(npix * nz * 8);
+    p.off_llo = take(nch * 8);
+    p.off_tw_scan = take(nz * 8);
+    p.off_tw_fine = take(static_cast<size_t>(p.n_fine) * 8);
+    p.off_deap = take(static_cast<size_t>(p.n_l) * 4);
+    p.off_kp = take(nz * nf * 8);
+    p.off_wk = take(nz * nf * 4);
+    p.off_mfma_a = off;
+    p.off_mfma_b = off;
+    p.total = off;
+    *out = p;
+    return PL_OK;
+}
+
+}  // namespace pl

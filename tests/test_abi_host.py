@@ -1,0 +1,156 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/polyrecon.h declares, builds the same array geometry as
+the oracle, plans the hybrid method sensibly and rejects bad arguments."""
+import math
+import os
+import re
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as ogeom
+
+pr = pytest.importorskip("paper_2109_02842_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+if not os.path.exists(pr.LIB_PATH):
+    pytest.skip("libpolyrecon.so not built", allow_module_level=True)
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "polyrecon.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    decl = _declared_functions()
+    assert len(decl) >= 15
+    lib = pr.lib()
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(pr.EXPORTED)
+
+
+@pytest.mark.parametrize("wl", [W.C1, W.C2, W.C3], ids=["C1", "C2", "C3"])
+def test_geometry_matches_oracle(wl):
+    g = pr.make_geometry(wl.array)
+    info = g.info()
+    arr = ogeom.build(wl.array)
+    assert g.n_channels == arr.n_channels
+    assert np.allclose(info["tx"], arr.tx, rtol=0, atol=1e-12)
+    assert np.allclose(info["rx"], arr.rx, rtol=0, atol=1e-12)
+    assert np.allclose(info["z_scan"], arr.z_scan, rtol=0, atol=1e-12)
+    assert np.array_equal(info["freq"], arr.freq)
+    assert np.allclose(info["chord_ends"], arr.chord_ends, rtol=0, atol=1e-12)
+
+
+def test_geometry_errors():
+    a = W.C1.array
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.make_geometry(replace(a, n_elem=400))          # chord longer than the diameter
+    assert e.value.code == pr.PL_EGEOM
+    for bad in (dict(n_chords=0), dict(spacing=-1.0), dict(f_stop=20e9), dict(n_scan=0),
+                dict(n_freq=5000), dict(mode="bistatic")):
+        with pytest.raises(pr.PolyreconError) as e:
+            pr.make_geometry(replace(a, **bad))
+        assert e.value.code == pr.PL_EINVAL
+    with pytest.raises(pr.PolyreconError):
+        pr.make_geometry(replace(W.C3.array, n_tx=3))       # no default placement for 3 Tx
+    g = pr.make_geometry(replace(W.C3.array, n_tx=3, tx_offsets=(-0.1, 0.0, 0.1)))
+    assert g.n_channels == 7 * 3 * 32
+    # null pointers through the raw ABI
+    assert pr.lib().make_geometry(None, None) == pr.PL_EINVAL
+    assert "null" in pr.last_error()
+    assert pr.lib().destroy_geometry(None) == pr.PL_OK
+
+
+@pytest.mark.parametrize("wl", [W.C1, W.C2, W.C3], ids=["C1", "C2", "C3"])
+def test_plan_is_consistent(wl):
+    g = pr.make_geometry(wl.array)
+    p = pr.hybrid_plan_info(g, wl.grid)
+    assert p.n_kz == wl.array.n_scan
+    assert p.n_fine == 2 * p.n_l and p.n_l % 2 == 0
+    assert p.kernel_width == 7                      # 1e-6 tolerance
+    assert p.n_blocks == math.ceil(wl.array.n_scan / 64)
+    # the range grid covers every channel's range span at the requested step
+    arr = ogeom.build(wl.array)
+    x = wl.grid.x0 + wl.grid.dx * np.array([0, wl.grid.nx - 1])
+    y = wl.grid.y0 + wl.grid.dy * np.array([0, wl.grid.ny - 1])
+    xx, yy = np.meshgrid(np.linspace(x[0], x[1], 41), np.linspace(y[0], y[1], 41))
+    l = (np.hypot(xx.ravel()[None] - arr.tx[:, :1], yy.ravel()[None] - arr.tx[:, 1:]) +
+         np.hypot(xx.ravel()[None] - arr.rx[:, :1], yy.ravel()[None] - arr.rx[:, 1:]))
+    assert (l.max(1) - l.min(1)).max() + 4 * p.du < p.n_l * p.du
+    # reference wavenumbers lie inside the propagating band k_rho in (0, k_max]
+    kmax = 2 * math.pi * wl.array.f_stop / W.SPEED_OF_LIGHT
+    assert all(0 < k <= kmax for k in p.k_ref)
+    # step: l_oversample samples per Nyquist interval of the widest block band
+    kz = 2 * np.pi * np.fft.fftfreq(wl.array.n_scan, wl.array.scan_step)
+    kf = 2 * np.pi * np.linspace(wl.array.f_start, wl.array.f_stop, wl.array.n_freq) / W.SPEED_OF_LIGHT
+    half = 0.0
+    for b in range(p.n_blocks):
+        kk = kz[b * 64:(b + 1) * 64]
+        kr = np.sqrt(np.maximum(kf[None] ** 2 - kk[:, None] ** 2 / 4, 0))
+        kr = kr[kr > 0]
+        half = max(half, (kr.max() - kr.min()) / 2)
+    assert math.isclose(p.du, math.pi / (8 * half), rel_tol=1e-12)
+    assert pr.hybrid_workspace_bytes(g, wl.grid) == p.workspace_bytes
+    assert p.workspace_bytes >= 8 * (arr.n_channels * wl.array.n_scan * (wl.array.n_freq + p.n_l))
+
+
+def test_plan_errors():
+    g = pr.make_geometry(W.C1.array)
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, replace(W.C1.grid, nx=0))
+    assert e.value.code == pr.PL_EINVAL
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, W.C1.grid, l_oversample=1.0)
+    assert e.value.code == pr.PL_EINVAL
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, W.C1.grid, nufft_tol=0.5)
+    assert e.value.code == pr.PL_EINVAL
+    g7 = pr.make_geometry(replace(W.C1.array, n_scan=7))     # no radix-7 FFT
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g7, W.C1.grid)
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(ValueError):
+        pr.hybrid_plan_info(g, W.C1.grid, precision="fp64")
+
+
+def test_sampling_criteria():
+    # C1's half-wavelength transceivers satisfy eq. (21)/2; doubling the
+    # spacing or the scan step beyond eq. (22) raises the warnings.
+    g = pr.make_geometry(W.C1.array)
+    assert pr.check_sampling(g, W.C1.grid) == 0
+    g2 = pr.make_geometry(replace(W.C1.array, spacing=3 * W.C1.array.spacing))
+    assert pr.check_sampling(g2, W.C1.grid) & pr.WARN_ELEMENT_SPACING
+    g3 = pr.make_geometry(replace(W.C1.array, scan_step=0.05))
+    assert pr.check_sampling(g3, W.C1.grid) & pr.WARN_SCAN_STEP
+
+
+def test_raw_abi_argument_errors_before_device_use():
+    # These paths return before any device access, so dummy pointers suffice.
+    import ctypes as C
+    L = pr.lib()
+    g = pr.make_geometry(W.C1.array)
+    grid = C.byref(pr._grid(W.C1.grid))
+    opts = C.byref(pr._opts())
+    fake = C.c_void_p(1 << 20)
+    need = pr.hybrid_workspace_bytes(g, W.C1.grid)
+    assert L.reconstruct_hybrid(g.handle, grid, opts, None, fake, fake, need, None) == pr.PL_EINVAL
+    assert L.reconstruct_hybrid(g.handle, grid, opts, fake, fake, None, need, None) == pr.PL_EWORKSPACE
+    assert L.reconstruct_hybrid(g.handle, grid, opts, fake, fake, fake, need - 1, None) == pr.PL_EWORKSPACE
+    assert "needed" in pr.last_error()
+    assert L.reconstruct_hybrid(g.handle, grid, opts, fake, fake, C.c_void_p((1 << 20) + 8), need,
+                                None) == pr.PL_EWORKSPACE
+    assert "aligned" in pr.last_error()
+    bad_opts = pr.HybridOpts(7, 0, 8.0, 1e-6)
+    assert L.reconstruct_hybrid(g.handle, grid, C.byref(bad_opts), fake, fake, fake, need, None) == pr.PL_EINVAL
+    assert L.reconstruct_bp(g.handle, grid, 0, 0, fake, fake, fake, 1 << 30, None) == pr.PL_EINVAL
+    assert L.reconstruct_bp(g.handle, grid, 20, 10, fake, fake, fake, 1 << 30, None) == pr.PL_EINVAL
+    assert L.reconstruct_bp(g.handle, grid, 0, 1, fake, fake, fake, 16, None) == pr.PL_EWORKSPACE
+    assert L.simulate_echo(g.handle, -1, fake, fake, fake, None) == pr.PL_EINVAL
+    assert L.simulate_echo(g.handle, 3, None, fake, fake, None) == pr.PL_EINVAL
+    assert L.scan_fft(None, fake, fake, None) == pr.PL_EINVAL
