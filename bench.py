@@ -90,6 +90,11 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bp", action="store_true")
     ap.add_argument("--bp-planes", type=int, default=2)
+    ap.add_argument("--tile", type=int, default=0, help="back-projection tile (0 = automatic)")
+    ap.add_argument("--interp", default="bspline4", choices=["bspline4", "lagrange4", "linear"])
+    ap.add_argument("--l-oversample", type=float, default=8.0)
+    ap.add_argument("--kz-per-lane", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -111,7 +116,8 @@ def main() -> int:
     pos, refl = W.scatterers(wl.scene)
     echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
     torch.cuda.synchronize()
-    opts = dict(precision=args.precision)
+    opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
+                l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves)
     plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
     ws = pr.workspace(plan.workspace_bytes)
     img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
@@ -161,7 +167,8 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
-                   "interp": "bspline4", "l_oversample": 8, "nufft_tol": 1e-6},
+                   "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
+                   "tile": list(plan.tile)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "backproject", "flop_per_launch": FLOP_PER_TERM * terms,

@@ -181,12 +181,26 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *   l_oversample  range-grid oversampling over the Nyquist rate of the
  *                 baseband range profile (default 8; >= 2).
  *   nufft_tol     NUFFT tolerance (default 1e-6; 1e-12 .. 1e-2).
+ *   tile          back-projection pixel tile edge: 0 = automatic, or 8, 4, 2
+ *                 (PL_EUNSUPPORTED if the forced tile's range window does not
+ *                 fit).
+ *   kz_per_lane   k_z bins per lane in the back-projection: 0 = automatic, or
+ *                 1, 2, 4.  64 x kz_per_lane bins share one reference
+ *                 wavenumber, so this also sets the range-grid step.
+ *   waves         wavefronts per back-projection workgroup: 0 = automatic, or
+ *                 4, 8 (8 only with the 8x8 tile).
+ * tile, kz_per_lane and waves are tuning knobs; results agree to the method's
+ * tolerance whatever their values.
  */
 typedef struct pl_hybrid_opts {
     int32_t precision;
     int32_t interp;
     double l_oversample;
     double nufft_tol;
+    int32_t tile;
+    int32_t kz_per_lane;
+    int32_t waves;
+    int32_t reserved;
 } pl_hybrid_opts;
 
 /* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */

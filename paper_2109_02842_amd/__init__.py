@@ -57,7 +57,8 @@ class ImageGridC(C.Structure):
 
 class HybridOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("interp", C.c_int32), ("l_oversample", C.c_double),
-                ("nufft_tol", C.c_double)]
+                ("nufft_tol", C.c_double), ("tile", C.c_int32), ("kz_per_lane", C.c_int32),
+                ("waves", C.c_int32), ("reserved", C.c_int32)]
 
 
 class HybridPlanInfo(C.Structure):
@@ -200,12 +201,14 @@ def _grid(grid) -> ImageGridC:
                       float(grid.dy))
 
 
-def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6) -> HybridOpts:
+def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
+          waves=0) -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {list(INTERPS)}")
-    return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol))
+    return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol),
+                      int(tile), int(kz_per_lane), int(waves), 0)
 
 
 def check_sampling(geom: Geometry, grid) -> int:

@@ -66,7 +66,7 @@ int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     info->n_fine = p.n_fine;
     info->kernel_width = p.W;
     info->n_blocks = p.n_blocks;
-    info->block = kBlock;
+    info->block = p.block;
     info->window = p.window;
     info->tile_x = p.tile_x;
     info->tile_y = p.tile_y;

@@ -17,9 +17,10 @@ namespace pl {
 
 constexpr double kSpeedOfLight = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kBlock = 64;          // k_z bins per block: one per lane of a wavefront
+constexpr int kLanes = 64;          // wavefront width on gfx950
 constexpr int kMaxScan = 4096;
-constexpr int kMaxBlocks = kMaxScan / kBlock;
+constexpr int kMaxBlocks = kMaxScan / kLanes;  // k_z blocks of at least one bin per lane
+constexpr size_t kMaxLds = 160 * 1024;          // LDS per workgroup on gfx950
 constexpr int kMaxFreq = 1024;
 constexpr int kMaxFine = 4096;      // NUFFT fine grid held twice in LDS (64 KiB)
 constexpr int kMaxGL = 64;          // quadrature nodes for the kernel transform
@@ -75,16 +76,18 @@ struct HybridPlan {
     double x0 = 0, y0 = 0, dx = 0, dy = 0;
     int precision = PL_PREC_FP32, interp = PL_INTERP_BSPLINE4;
     double sigma_l = 8.0, tol = 1e-6;
+    int force_tile = 0, force_kpl = 0, force_waves = 0;
     // range grid and NUFFT
     int n_l = 0, n_fine = 0, W = 0;
     double du = 0, h = 0, beta = 0;
+    int block = kLanes;  // k_z bins sharing one reference wavenumber (64 x bins per lane)
     int n_blocks = 0;
     double kref[kMaxBlocks] = {};
     Radices scan_rad, fine_rad;
     int n_gl = 0;
     double gl_x[kMaxGL] = {}, gl_w[kMaxGL] = {};
     // back-projection tiling
-    int tile_x = 8, tile_y = 8, tiles_x = 0, tiles_y = 0, window = 0, window_pad = 0;
+    int tile_x = 8, tile_y = 8, tiles_x = 0, tiles_y = 0, window = 0, window_pad = 0, waves = 4;
     // interpolation weights w_k(t) = sum_j coef[k][j] t^j, taps at floor(u)-1+k
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
@@ -92,6 +95,7 @@ struct HybridPlan {
     size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, total = 0;
 };
 
+size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
               HybridPlan* p);
 

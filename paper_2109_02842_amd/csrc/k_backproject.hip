@@ -10,8 +10,9 @@
 // pair (range in float64, carrier phase range-reduced in float64) by one
 // lane each and broadcast with readlane; every k_z bin then costs four LDS
 // reads and twelve FMAs.  The channel's range window for the tile is staged
-// in LDS (double-buffered: the next channel's rows are loaded into registers
-// while the current one is consumed).  Blocks are assigned so that each XCD
+// in LDS, double-buffered: the next channel's rows are copied into the other
+// buffer before the current one is consumed (the other resident waves hide
+// the load latency), one barrier per channel.  Blocks are assigned so that each XCD
 // works on a contiguous range of (k_z block, tile) work items, which keeps
 // the range profiles it reads in its own L2.
 #include "device.hpp"
@@ -20,45 +21,63 @@ namespace pl {
 namespace {
 
 struct BpjArgs {
-    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, window, wpad, pad_;
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, window, wpad, rows;
     double x0, y0, dx, dy, du, inv_du, reach;
     float coef[4][4];
     double kref[kMaxBlocks];
 };
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+// gfx9 raw-buffer descriptor word 3: 32-bit data format, no swizzle
+constexpr int kBufferFlags = 0x00020000;
+
+__device__ __forceinline__ float2 load_c64(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
 __device__ __forceinline__ float rdl(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-template <int TX, int TY, int E>
-__global__ __launch_bounds__(256) void backproject_kernel(const float2* __restrict__ q,
-                                                          const double* __restrict__ chan,
-                                                          const double* __restrict__ llo, BpjArgs a,
-                                                          float2* __restrict__ G) {
-    constexpr int PPW = TX * TY / 4;  // pixels per wavefront
-    constexpr int CPB = 64 / PPW;     // channels per weight batch
-    static_assert(PPW * CPB == 64, "tile must give 1, 4 or 16 pixels per wavefront");
+// TX x TY pixel tile, KPL k_z bins per lane (a block of 64 * KPL bins shares
+// one reference wavenumber), NW wavefronts per block, OCC the wavefronts per
+// SIMD the LDS footprint allows (it caps the registers at 512 / OCC).
+template <int TX, int TY, int KPL, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) void backproject_kernel(const float2* __restrict__ q,
+                                                              const double* __restrict__ chan,
+                                                              const double* __restrict__ llo, BpjArgs a,
+                                                              float2* __restrict__ G) {
+    constexpr int NT = 64 * NW;
+    constexpr int PPW = TX * TY / NW;   // pixels per wavefront
+    constexpr int CPB = 64 / PPW;       // channels per weight batch
+    constexpr int ROWS = 64 * KPL;      // k_z rows staged per channel
+    constexpr int RPW = ROWS / NW;      // rows staged by each wavefront
+    constexpr int PASS = RPW < 16 ? RPW : 16;
+    static_assert(PPW * CPB == 64, "a weight batch must fill the wavefront");
+    static_assert(RPW % PASS == 0, "rows per wavefront");
     extern __shared__ int smem_i[];
     int* win = smem_i;                                                            // n_ch window starts
-    float2* qbuf = reinterpret_cast<float2*>(smem_i + ((a.n_ch + 63) & ~63));     // [2][64][wpad]
+    float2* qbuf = reinterpret_cast<float2*>(smem_i + ((a.n_ch + 63) & ~63));     // [2][ROWS][wpad]
 
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
     if (work >= a.n_work) return;  // block-uniform, before any barrier
     const int blk = work / a.n_tiles;
     const int tile = work - blk * a.n_tiles;
     const int tx0 = (tile % a.tiles_x) * TX, ty0 = (tile / a.tiles_x) * TY;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int kap = blk * 64 + lane;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
     const double kref_rev = a.kref[blk] * (0.5 / kPi);
-    const int buf_stride = 64 * a.wpad;
+    const int buf_stride = ROWS * a.wpad;
 
     // window start of every channel for this tile
     {
         const double cx = a.x0 + (tx0 + 0.5 * (TX - 1)) * a.dx;
         const double cy = a.y0 + (ty0 + 0.5 * (TY - 1)) * a.dy;
-        for (int c = tid; c < a.n_ch; c += 256) {
+        for (int c = tid; c < a.n_ch; c += NT) {
             const double* ch = chan + 4 * c;
-            const double l = hypot(cx - ch[0], cy - ch[1]) + hypot(cx - ch[2], cy - ch[3]);
+            const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
+                             sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
             int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 1;
             s = max(0, min(s, a.n_l - a.window));
             win[c] = s;
@@ -66,41 +85,53 @@ __global__ __launch_bounds__(256) void backproject_kernel(const float2* __restri
     }
     __syncthreads();
 
-    // staging: wavefront w moves rows kz_local in [16w, 16w + 16)
-    float2 stage[16][E];
-    auto load_rows = [&](int c) {
-        const int s0 = win[c];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int kl = wave * 16 + r;
-            const int kz = blk * 64 + kl;
-            const float2* src = q + (static_cast<size_t>(c) * a.n_z + kz) * a.n_l + s0;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int i = lane + 64 * e;
-                stage[r][e] = (kz < a.n_z && i < a.window) ? src[i] : make_float2(0.f, 0.f);
-            }
-        }
-    };
-    auto store_rows = [&](int buf) {
-        float2* dst = qbuf + buf * buf_stride;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int kl = wave * 16 + r;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int i = lane + 64 * e;
-                if (i < a.window) dst[kl * a.wpad + i] = stage[r][e];
-            }
-        }
-    };
+    // Staging: wavefront w copies rows [w * RPW, (w + 1) * RPW) of the k_z
+    // block.  Every load stays in bounds: rows past the last k_z bin repeat it
+    // and lanes past the window repeat its last sample; only the LDS stores
+    // are predicated (repeated rows feed lanes whose results are dropped).
+    const int kz_first = blk * ROWS + wave * RPW;
+    const int ie0 = min(lane, a.window - 1);
+    const int ie1 = min(lane + 64, a.window - 1);
+    // Rows are read with buffer loads: a uniform descriptor for the channel's
+    // slab q[c][:][:], a 32-bit lane offset and a scalar row offset, so no
+    // per-lane 64-bit addresses are kept live.
+    float2 stage[PASS];
+    const unsigned slab_bytes = static_cast<unsigned>(a.n_z) * a.n_l * 8u;
+    const unsigned row_bytes = static_cast<unsigned>(a.n_l) * 8u;
+#define PL_STAGE(C_, BUF_)                                                                    \
+    {                                                                                         \
+        const int s0_ = __builtin_amdgcn_readfirstlane(win[C_]);                              \
+        const __amdgpu_buffer_rsrc_t rs_ = __builtin_amdgcn_make_buffer_rsrc(                 \
+            const_cast<float2*>(q + static_cast<size_t>(C_) * a.n_z * a.n_l), 0, slab_bytes, \
+            kBufferFlags);                                                                    \
+        const unsigned v0_ = static_cast<unsigned>(s0_ + ie0) * 8u;                           \
+        const unsigned v1_ = static_cast<unsigned>(s0_ + ie1) * 8u;                           \
+        float2* dst_ = qbuf + (BUF_) * buf_stride + wave * RPW * a.wpad;                      \
+        _Pragma("unroll") for (int r0 = 0; r0 < RPW; r0 += PASS) {                            \
+            _Pragma("unroll") for (int r = 0; r < PASS; ++r) {                                \
+                const unsigned so_ = static_cast<unsigned>(min(kz_first + r0 + r, a.n_z - 1)) * row_bytes; \
+                stage[r] = load_c64(rs_, v0_, so_);                                           \
+            }                                                                                 \
+            _Pragma("unroll") for (int r = 0; r < PASS; ++r)                                  \
+                if (lane < a.window) dst_[(r0 + r) * a.wpad + lane] = stage[r];               \
+            if (a.window > 64) {                                                              \
+                _Pragma("unroll") for (int r = 0; r < PASS; ++r) {                            \
+                    const unsigned so_ = static_cast<unsigned>(min(kz_first + r0 + r, a.n_z - 1)) * row_bytes; \
+                    stage[r] = load_c64(rs_, v1_, so_);                                       \
+                }                                                                             \
+                _Pragma("unroll") for (int r = 0; r < PASS; ++r)                              \
+                    if (lane + 64 < a.window) dst_[(r0 + r) * a.wpad + lane + 64] = stage[r]; \
+            }                                                                                 \
+        }                                                                                     \
+    }
 
-    float2 acc[PPW];
+    float2 acc[PPW][KPL];
 #pragma unroll
-    for (int j = 0; j < PPW; ++j) acc[j] = make_float2(0.f, 0.f);
+    for (int j = 0; j < PPW; ++j)
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) acc[j][r] = make_float2(0.f, 0.f);
 
-    load_rows(0);
-    store_rows(0);
+    PL_STAGE(0, 0)
     __syncthreads();
 
     // this lane's pixel in the weight batches
@@ -110,15 +141,18 @@ __global__ __launch_bounds__(256) void backproject_kernel(const float2* __restri
     const bool pvalid = px < a.nx && py < a.ny;
     const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
 
+#pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += CPB) {
-        // weights of (pixel pj, channel c0 + lane / PPW)
+        // weights of (pixel pj, channel c0 + lane / PPW): range in float64,
+        // taps and cubic weights, carrier exp(j k_ref l) with float64 phase
         int my_i0 = 0;
         float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, cr = 0.f, ci = 0.f;
         {
             const int c = c0 + lane / PPW;
             if (c < a.n_ch && pvalid) {
                 const double* ch = chan + 4 * c;
-                const double l = hypot(xg - ch[0], yg - ch[1]) + hypot(xg - ch[2], yg - ch[3]);
+                const double l = sqrt((xg - ch[0]) * (xg - ch[0]) + (yg - ch[1]) * (yg - ch[1])) +
+                                 sqrt((xg - ch[2]) * (xg - ch[2]) + (yg - ch[3]) * (yg - ch[3]));
                 const double u = (l - llo[c]) * a.inv_du;
                 const double fl = floor(u);
                 const float t = static_cast<float>(u - fl);
@@ -133,11 +167,11 @@ __global__ __launch_bounds__(256) void backproject_kernel(const float2* __restri
                 ci = car.y;
             }
         }
+#pragma unroll 1
         for (int cc = 0; cc < CPB; ++cc) {
             const int c = c0 + cc;
             if (c >= a.n_ch) break;
-            const bool more = c + 1 < a.n_ch;
-            if (more) load_rows(c + 1);
+            if (c + 1 < a.n_ch) PL_STAGE(c + 1, (c + 1) & 1)
             const float2* base = qbuf + (c & 1) * buf_stride + lane * a.wpad;
 #pragma unroll
             for (int j = 0; j < PPW; ++j) {
@@ -145,42 +179,57 @@ __global__ __launch_bounds__(256) void backproject_kernel(const float2* __restri
                 const int i0 = __builtin_amdgcn_readlane(my_i0, L);
                 const float v0 = rdl(w0, L), v1 = rdl(w1, L), v2 = rdl(w2, L), v3 = rdl(w3, L);
                 const float kr = rdl(cr, L), ki = rdl(ci, L);
-                const float2 q0 = base[i0], q1 = base[i0 + 1], q2 = base[i0 + 2], q3 = base[i0 + 3];
-                const float re = v0 * q0.x + v1 * q1.x + v2 * q2.x + v3 * q3.x;
-                const float im = v0 * q0.y + v1 * q1.y + v2 * q2.y + v3 * q3.y;
-                acc[j].x += kr * re - ki * im;
-                acc[j].y += kr * im + ki * re;
+                const float2* b = base + i0;
+#pragma unroll
+                for (int r = 0; r < KPL; ++r) {
+                    const float2* br = b + r * 64 * a.wpad;
+                    const float2 q0 = br[0], q1 = br[1], q2 = br[2], q3 = br[3];
+                    const float re = v0 * q0.x + v1 * q1.x + v2 * q2.x + v3 * q3.x;
+                    const float im = v0 * q0.y + v1 * q1.y + v2 * q2.y + v3 * q3.y;
+                    acc[j][r].x = fmaf(kr, re, acc[j][r].x);
+                    acc[j][r].x = fmaf(-ki, im, acc[j][r].x);
+                    acc[j][r].y = fmaf(kr, im, acc[j][r].y);
+                    acc[j][r].y = fmaf(ki, re, acc[j][r].y);
+                }
             }
-            if (more) store_rows((c + 1) & 1);
             __syncthreads();
         }
     }
+#undef PL_STAGE
 
-    if (kap < a.n_z) {
 #pragma unroll
-        for (int j = 0; j < PPW; ++j) {
-            const int l = wave * PPW + j;
-            const int x = tx0 + l % TX, y = ty0 + l / TX;
-            if (x < a.nx && y < a.ny) G[(static_cast<size_t>(y) * a.nx + x) * a.n_z + kap] = acc[j];
+    for (int j = 0; j < PPW; ++j) {
+        const int l = wave * PPW + j;
+        const int x = tx0 + l % TX, y = ty0 + l / TX;
+        if (x < a.nx && y < a.ny) {
+#pragma unroll
+            for (int r = 0; r < KPL; ++r) {
+                const int kz = blk * ROWS + lane + 64 * r;
+                if (kz < a.n_z) G[(static_cast<size_t>(y) * a.nx + x) * a.n_z + kz] = acc[j][r];
+            }
         }
     }
 }
 
-template <int TX, int TY, int E>
-int launch_tile(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
-                const double* chan, const double* llo, float2* G) {
-    auto fn = backproject_kernel<TX, TY, E>;
+template <int TX, int TY, int KPL, int NW, int OCC>
+int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
+                   const double* chan, const double* llo, float2* G) {
+    auto fn = backproject_kernel<TX, TY, KPL, NW, OCC>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(smem));
         if (e != hipSuccess) return fail(PL_EDEVICE, "back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), smem, s, q, chan, llo, a, G);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, q, chan, llo, a, G);
     return check_launch("back-projection");
 }
 
 }  // namespace
+
+size_t backproject_lds_bytes(int n_ch, int rows, int window_pad) {
+    return static_cast<size_t>((n_ch + 63) & ~63) * 4 + 2ull * rows * window_pad * 8;
+}
 
 int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws, float2* G,
                        hipStream_t s) {
@@ -196,6 +245,7 @@ int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2
     a.per_xcd = (a.n_work + 7) / 8;
     a.window = p.window;
     a.wpad = p.window_pad;
+    a.rows = p.block;
     a.x0 = p.x0;
     a.y0 = p.y0;
     a.dx = p.dx;
@@ -206,23 +256,25 @@ int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2
     for (int k = 0; k < 4; ++k)
         for (int j = 0; j < 4; ++j) a.coef[k][j] = p.coef[k][j];
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
+    if (static_cast<unsigned long long>(p.n_z) * p.n_l * 8 >= (1ull << 31))
+        return fail(PL_EUNSUPPORTED, "range profiles of one channel exceed 2 GiB");
     if (p.window < 4 || p.window > 128 || p.window > p.n_l)
         return fail(PL_EUNSUPPORTED, "back-projection window %d out of range", p.window);
-    const size_t smem = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * 64 * p.window_pad * 8;
-    if (smem > 160 * 1024) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
+    const size_t smem = backproject_lds_bytes(p.n_ch, p.block, p.window_pad);
+    if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
-    const bool two = p.window > 64;
-    if (p.tile_x == 8 && p.tile_y == 8)
-        return two ? launch_tile<8, 8, 2>(a, smem, blocks, s, q, dt.chan, llo, G)
-                   : launch_tile<8, 8, 1>(a, smem, blocks, s, q, dt.chan, llo, G);
-    if (p.tile_x == 4 && p.tile_y == 4)
-        return two ? launch_tile<4, 4, 2>(a, smem, blocks, s, q, dt.chan, llo, G)
-                   : launch_tile<4, 4, 1>(a, smem, blocks, s, q, dt.chan, llo, G);
-    if (p.tile_x == 2 && p.tile_y == 2)
-        return two ? launch_tile<2, 2, 2>(a, smem, blocks, s, q, dt.chan, llo, G)
-                   : launch_tile<2, 2, 1>(a, smem, blocks, s, q, dt.chan, llo, G);
-    return fail(PL_EUNSUPPORTED, "no back-projection kernel for a %dx%d tile", p.tile_x, p.tile_y);
+    const int kpl = p.block / kLanes;
+#define PL_CASE(TX, TY, K, NW, OCC)                                                   \
+    if (p.tile_x == TX && p.tile_y == TY && kpl == K && p.waves == NW)                \
+        return launch_variant<TX, TY, K, NW, OCC>(a, smem, blocks, s, q, dt.chan, llo, G);
+    PL_CASE(8, 8, 1, 4, 4) PL_CASE(8, 8, 2, 4, 2) PL_CASE(8, 8, 4, 4, 1)
+    PL_CASE(8, 8, 1, 8, 4) PL_CASE(8, 8, 2, 8, 4) PL_CASE(8, 8, 4, 8, 2)
+    PL_CASE(4, 4, 1, 4, 4) PL_CASE(4, 4, 2, 4, 2) PL_CASE(4, 4, 4, 4, 1)
+    PL_CASE(2, 2, 1, 4, 4) PL_CASE(2, 2, 2, 4, 2) PL_CASE(2, 2, 4, 4, 1)
+#undef PL_CASE
+    return fail(PL_EUNSUPPORTED, "no back-projection kernel for tile %dx%d, %d k_z per lane, %d waves", p.tile_x,
+                p.tile_y, kpl, p.waves);
 }
 
 }  // namespace pl

@@ -6,7 +6,7 @@ namespace pl {
 namespace {
 
 struct PlanTablesArgs {
-    int n_ch, n_z, n_f, n_l, n_fine, interp, n_gl, pad_;
+    int n_ch, n_z, n_f, n_l, n_fine, interp, n_gl, block;
     double du, h, beta, scan_step;
     double gx0, gx1, gy0, gy1;
     double kref[kMaxBlocks];
@@ -67,7 +67,7 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
             const double arg = k[f] * k[f] - 0.25 * kz * kz;
             const bool valid = arg > 0.0;
             const double kr = valid ? sqrt(arg) : 0.0;
-            const double kpr = kr - a.kref[kap / kBlock];
+            const double kpr = kr - a.kref[kap / a.block];
             kp[e] = kpr;
             double w = valid ? k[f] : 0.0;
             if (valid && a.interp == PL_INTERP_BSPLINE4) {
@@ -181,6 +181,7 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
     a.n_fine = p.n_fine;
     a.interp = p.interp;
     a.n_gl = p.n_gl;
+    a.block = p.block;
     a.du = p.du;
     a.h = p.h;
     a.beta = p.beta;

@@ -67,7 +67,16 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.interp = opts->interp;
         if (opts->l_oversample != 0) p.sigma_l = opts->l_oversample;
         if (opts->nufft_tol != 0) p.tol = opts->nufft_tol;
+        p.force_tile = opts->tile;
+        p.force_kpl = opts->kz_per_lane;
+        p.force_waves = opts->waves;
     }
+    if (p.force_kpl != 0 && p.force_kpl != 1 && p.force_kpl != 2 && p.force_kpl != 4)
+        return fail(PL_EINVAL, "kz_per_lane must be 0, 1, 2 or 4");
+    if (p.force_waves != 0 && p.force_waves != 4 && p.force_waves != 8)
+        return fail(PL_EINVAL, "waves must be 0, 4 or 8");
+    if (p.force_tile != 0 && p.force_tile != 8 && p.force_tile != 4 && p.force_tile != 2)
+        return fail(PL_EINVAL, "tile must be 0, 8, 4 or 2");
     if (p.precision < PL_PREC_FP32 || p.precision > PL_PREC_FP16)
         return fail(PL_EINVAL, "unknown precision %d", p.precision);
     if (p.interp < PL_INTERP_BSPLINE4 || p.interp > PL_INTERP_LINEAR)
@@ -82,11 +91,16 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // One reference wavenumber per block of k_z bins: the centre of the band
     // of k_rho it spans.  The reference cancels exactly between eqs. (8a) and
     // (8b); only the bandwidth of the range profiles depends on it.
-    p.n_blocks = (p.n_z + kBlock - 1) / kBlock;
+    // One k_z bin per lane by default: measured fastest on gfx950, since more
+    // bins per lane make the staged window too large for several resident
+    // workgroups per CU.
+    const int kpl = p.force_kpl ? p.force_kpl : 1;
+    p.block = kLanes * kpl;
+    p.n_blocks = (p.n_z + p.block - 1) / p.block;
     double half_band = 0.0;
     for (int b = 0; b < p.n_blocks; ++b) {
         double lo = 1e300, hi = -1e300;
-        for (int kap = b * kBlock; kap < std::min(p.n_z, (b + 1) * kBlock); ++kap) {
+        for (int kap = b * p.block; kap < std::min(p.n_z, (b + 1) * p.block); ++kap) {
             const int sk = kap < (p.n_z + 1) / 2 ? kap : kap - p.n_z;
             const double kz = 2.0 * kPi * sk / (p.n_z * g->scan_step);
             for (int f = 0; f < p.n_f; ++f) {
@@ -124,21 +138,29 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
 
     // Back-projection tile: the staged range window must hold every tap of
     // the tile's pixels.  |l(p) - l(centre)| <= 2 * half-diagonal.
-    // Prefer the largest tile whose window fits 128 samples and whose LDS
-    // (window starts + two staged windows of 64 rows) stays within 64 KiB.
+    // Prefer the largest tile whose window fits 64 samples (one staging load
+    // per lane and row; the 2x2 fallback allows 128) and whose LDS (window
+    // starts + two staged windows of 64 x kz_per_lane rows) fits the
+    // workgroup's 160 KiB.
     const int tiles[3][2] = {{8, 8}, {4, 4}, {2, 2}};
     p.window = 0;
     for (int t = 0; t < 3; ++t) {
+        if (p.force_tile && tiles[t][0] != p.force_tile) continue;
         const double rt = 0.5 * std::hypot((tiles[t][0] - 1) * grid->dx, (tiles[t][1] - 1) * grid->dy);
         const int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
-        const size_t lds = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * 64 * (wl | 1) * 8;
-        if ((wl <= 128 && lds <= 65536) || t == 2) {
+        const size_t lds = backproject_lds_bytes(p.n_ch, p.block, wl | 1);
+        if ((wl <= (t == 2 ? 128 : 64) && lds <= kMaxLds) || t == 2 || p.force_tile) {
             p.tile_x = tiles[t][0];
             p.tile_y = tiles[t][1];
             p.window = wl;
             break;
         }
     }
+    p.waves = p.force_waves ? p.force_waves : 4;
+    if (p.waves == 8 && p.tile_x != 8)
+        return fail(PL_EUNSUPPORTED, "8 wavefronts per workgroup need the 8x8 tile");
+    if (backproject_lds_bytes(p.n_ch, p.block, p.window | 1) > kMaxLds)
+        return fail(PL_EUNSUPPORTED, "back-projection staging exceeds the LDS (lower kz_per_lane)");
     if (p.window > 128)
         return fail(PL_EUNSUPPORTED, "pixels are too coarse for the range grid (window %d > 128)", p.window);
     p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes

@@ -74,7 +74,8 @@ def test_plan_is_consistent(wl):
     assert p.n_kz == wl.array.n_scan
     assert p.n_fine == 2 * p.n_l and p.n_l % 2 == 0
     assert p.kernel_width == 7                      # 1e-6 tolerance
-    assert p.n_blocks == math.ceil(wl.array.n_scan / 64)
+    assert p.block % 64 == 0
+    assert p.n_blocks == math.ceil(wl.array.n_scan / p.block)
     # the range grid covers every channel's range span at the requested step
     arr = ogeom.build(wl.array)
     x = wl.grid.x0 + wl.grid.dx * np.array([0, wl.grid.nx - 1])
@@ -91,7 +92,7 @@ def test_plan_is_consistent(wl):
     kf = 2 * np.pi * np.linspace(wl.array.f_start, wl.array.f_stop, wl.array.n_freq) / W.SPEED_OF_LIGHT
     half = 0.0
     for b in range(p.n_blocks):
-        kk = kz[b * 64:(b + 1) * 64]
+        kk = kz[b * p.block:(b + 1) * p.block]
         kr = np.sqrt(np.maximum(kf[None] ** 2 - kk[:, None] ** 2 / 4, 0))
         kr = kr[kr > 0]
         half = max(half, (kr.max() - kr.min()) / 2)
