@@ -95,6 +95,8 @@ def main() -> int:
     ap.add_argument("--l-oversample", type=float, default=8.0)
     ap.add_argument("--kz-per-lane", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -119,41 +121,58 @@ def main() -> int:
     opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
                 l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves)
     plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
-    ws = pr.workspace(plan.workspace_bytes)
     img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
     log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
         f"tile={plan.tile} du={plan.du * 1e3:.3f} mm workspace={plan.workspace_bytes / 2**20:.1f} MiB")
 
-    # first call: device tables are uploaded lazily (plan build)
-    t0 = time.perf_counter()
-    pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
-    torch.cuda.synchronize()
-    first_ms = (time.perf_counter() - t0) * 1e3
-    for _ in range(args.warmup):
+    def time_path(opts, steps, warmup):
+        plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
+        ws = pr.workspace(plan.workspace_bytes)
+        t0 = time.perf_counter()
         pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
-    torch.cuda.synchronize()
-    log(f"[bench] warm-up done ({args.warmup} steps)")
+        torch.cuda.synchronize()
+        first_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(warmup):
+            pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        for row in evs:
+            for e in row:
+                e.record(stream)   # creates the underlying hipEvent
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for k in range(steps):
+            pr.reconstruct_hybrid_events(geom, wl.grid, echo, evs[k], out=img, ws=ws, **opts)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        stage = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+                 for i, name in enumerate(pr.STAGES)}
+        steps_ms = [evs[k][0].elapsed_time(evs[k][5]) for k in range(steps)]
+        del ws
+        return ms, stage, first_ms, float(np.median(steps_ms)), plan
 
-    stream = torch.cuda.current_stream()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    for row in evs:
-        for e in row:
-            e.record(stream)   # creates the underlying hipEvent
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    start.record(stream)
-    for k in range(args.steps):
-        pr.reconstruct_hybrid_events(geom, wl.grid, echo, evs[k], out=img, ws=ws, **opts)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - w0) * 1e3
-    total_ms = start.elapsed_time(stop)
-    ms = total_ms / args.steps
-    steps_ms = [evs[k][0].elapsed_time(evs[k][5]) for k in range(args.steps)]
-    stage = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-             for i, name in enumerate(pr.STAGES)}
-    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step (median {np.median(steps_ms):.3f}), wall {wall_ms:.1f} ms; "
+    def parity(opts):
+        """Relative L2 error against the FP64 oracle on sampled (k_z, pixel)
+        pairs of the spectrum, for a seeded CN(0,1) echo of this workload."""
+        from oracle import geometry as ogeom
+        from oracle import hybrid as ohyb
+        s = W.random_echo(a, 4242)
+        out = pr.reconstruct_hybrid(geom, wl.grid, torch.from_numpy(s).cuda(), **opts)
+        npix = wl.grid.nx * wl.grid.ny
+        pix = W.random_subset(npix, 128, 4243)
+        cols = out.reshape(a.n_scan, npix)[:, torch.from_numpy(pix).cuda()].cpu().numpy()
+        kap = sorted(set(W.random_subset(a.n_scan, 2, 4244).tolist() + [0]))
+        got = np.fft.fft(cols.astype(np.complex128), axis=0)[kap]
+        arr = ogeom.build(a)
+        px, py = ohyb.pixel_grid(wl.grid)
+        ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
+        return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), f"{len(kap)} k_z x {pix.size} pixels"
+
+    ms, stage, first_ms, med_ms, plan = time_path(opts, args.steps, args.warmup)
+    log(f"[bench] {args.precision}: {args.steps} steps {ms:.3f} ms/step (median {med_ms:.3f}); "
         + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
 
     voxels = wl.grid.nx * wl.grid.ny * a.n_scan
@@ -168,7 +187,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
-                   "tile": list(plan.tile)},
+                   "tile": list(plan.tile), "kz_block": plan.block},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "backproject", "flop_per_launch": FLOP_PER_TERM * terms,
@@ -176,6 +195,24 @@ def main() -> int:
         "stages_ms": stage,
         "plan_build_ms": first_ms,
     }
+    if not args.no_parity:
+        err, sample = parity(opts)
+        out["rel_l2_vs_oracle"] = {"value": err, "sample": sample, "echo": "seeded CN(0,1)"}
+        log(f"[bench] {args.precision}: rel L2 vs oracle {err:.2e} ({sample})")
+    if not args.no_variants:
+        out["variants"] = {}
+        for prec in ("bf16", "fp16", "fp32"):
+            if prec == args.precision:
+                continue
+            vopts = dict(opts, precision=prec)
+            vms, vstage, _, vmed, _ = time_path(vopts, args.steps, 1)
+            v = {"value": voxels / (vms * 1e-3), "ms_per_step": vms, "stages_ms": vstage,
+                 "speedup_vs_main": ms / vms}
+            if not args.no_parity:
+                v["rel_l2_vs_oracle"], _ = parity(vopts)
+            out["variants"][prec] = v
+            log(f"[bench] {prec}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
+                f"rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}")
 
     if not args.no_bp:
         nz = max(1, min(args.bp_planes, a.n_scan))
@@ -184,6 +221,7 @@ def main() -> int:
         bimg = torch.empty((nz, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
         pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=1, out=bimg[:1], ws=bws)
         torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=nz, out=bimg, ws=bws)

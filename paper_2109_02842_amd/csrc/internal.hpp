@@ -71,6 +71,7 @@ namespace pl {
 // kernels need, and the workspace layout.
 struct HybridPlan {
     int mode = 0, n_ch = 0, n_z = 0, n_f = 0;
+    int n_chp = 0, n_fp = 0;  // channels padded to 32, frequencies to 16 (MFMA tiles)
     double scan_step = 0;
     int nx = 0, ny = 0;
     double x0 = 0, y0 = 0, dx = 0, dy = 0;

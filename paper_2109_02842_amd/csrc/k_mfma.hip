@@ -1,10 +1,230 @@
-// Range compression as a dense contraction on the matrix cores (BF16 / FP16).
+// Range compression, eq. (8a) / (19a), as a dense contraction on the matrix
+// cores.  For one k_z bin the range profiles of all channels are
+//   Q[i][c] = sum_f A[i][f] C[f][c],  A[i][f] = exp(j k'_f u_i),
+//   C[f][c] = w_f S[c][kz][f] exp(j k'_f l_mid[c]),  u_i = (i - n_l/2) du,
+// i.e. the direct nonuniform DFT the NUFFT approximates, cast as a complex
+// GEMM with M = n_l, N = n_ch, K = n_f.  Complex products use the real
+// embedding with one phasor operand A' = [Re A | -Im A] (K' = 2 n_f):
+//   Re Q = A' [Re C; Im C],   Im Q = A' [Im C; -Re C].
+// Operands are BF16 or FP16 split into hi + lo parts (x = hi + lo, each
+// rounded to nearest), and each product is hi*hi + hi*lo + lo*hi with FP32
+// accumulation in the matrix cores (v_mfma_f32_32x32x16_{bf16,f16}).  The
+// phasor phase k'_f u_i is formed in float64 and range-reduced before the
+// float32 sin/cos.  FP16 strengths carry a power-of-2 scale per (k_z,
+// channel) so their largest part sits near 2^14.
 #include "device.hpp"
 
 namespace pl {
+namespace {
 
-int launch_range_compress_mfma(const HybridPlan&, const float2*, char*, float2*, hipStream_t) {
-    return fail(PL_EUNSUPPORTED, "MFMA range compression is not built yet");
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool F16>
+struct Half;
+template <>
+struct Half<false> {
+    typedef __bf16 T;
+    typedef bf16x8 V;
+    static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Half<true> {
+    typedef _Float16 T;
+    typedef f16x8 V;
+    static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+struct MfmaArgs {
+    int n_ch, n_chp, n_z, n_f, n_fp, n_l;
+    double du;
+};
+
+// Strengths C[f][c] for one (k_z, channel) per wavefront, split into
+// hi / lo parts of Re and Im: cs[((kz * n_chp + c) * 4 + part) * n_fp + f],
+// part 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo; padded frequencies and channels
+// are zero.  se[kz * n_chp + c] is the power-of-2 scale exponent.
+template <bool F16>
+__global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict__ spec,
+                                                        const double* __restrict__ llo,
+                                                        const double* __restrict__ kp,
+                                                        const float* __restrict__ wk, MfmaArgs a,
+                                                        typename Half<F16>::T* __restrict__ cs,
+                                                        int* __restrict__ se) {
+    typedef typename Half<F16>::T T;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wid >= a.n_z * a.n_chp) return;
+    const int kap = wid / a.n_chp, c = wid - kap * a.n_chp;
+    float2 v[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};  // n_fp <= 128
+    float mx = 0.f;
+    if (c < a.n_ch) {
+        const double lmid = llo[c] + (a.n_l / 2) * a.du;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = lane + 64 * h;
+            if (f < a.n_f) {
+                const size_t e = static_cast<size_t>(kap) * a.n_f + f;
+                const float2 s = spec[(static_cast<size_t>(c) * a.n_z + kap) * a.n_f + f];
+                v[h] = cscale(cmul(s, cis(kp[e] * lmid)), wk[e]);
+                mx = fmaxf(mx, fmaxf(fabsf(v[h].x), fabsf(v[h].y)));
+            }
+        }
+    }
+    int ex = 0;
+    if (F16) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        if (mx > 0.f) ex = min(max(14 - ilogbf(mx), -100), 100);
+    }
+    const float sc = ldexpf(1.f, ex);
+    T* dst = cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int f = lane + 64 * h;
+        if (f < a.n_fp) {
+            const float re = v[h].x * sc, im = v[h].y * sc;
+            const T rh = static_cast<T>(re), ih = static_cast<T>(im);
+            dst[f] = rh;
+            dst[a.n_fp + f] = static_cast<T>(re - static_cast<float>(rh));
+            dst[2 * a.n_fp + f] = ih;
+            dst[3 * a.n_fp + f] = static_cast<T>(im - static_cast<float>(ih));
+        }
+    }
+    if (lane == 0) se[wid] = ex;
+}
+
+__device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
+
+// One block = one k_z bin x 128 range samples; wavefront w owns rows
+// [32 w, 32 w + 32) of that range block and keeps its phasor operand A' for
+// all of K' in registers, then walks the channel tiles of 32.
+template <bool F16, int NCH>
+__global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16>::T* __restrict__ cs,
+                                                         const int* __restrict__ se,
+                                                         const double* __restrict__ kp, MfmaArgs a,
+                                                         float2* __restrict__ q) {
+    typedef typename Half<F16>::T T;
+    typedef typename Half<F16>::V V;
+    constexpr int NC = NCH;          // chunks of 16 in K' = 2 n_fp, NC = n_fp / 8
+    constexpr int HC = NC / 2;       // chunks per half (Re part / Im part)
+    const int n_ib = (a.n_l + 127) / 128;
+    const int kap = blockIdx.x / n_ib;
+    const int ib = blockIdx.x - kap * n_ib;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = ib * 128 + wave * 32;
+    if (row0 >= a.n_l) return;  // no barriers in this kernel
+    const int i = row0 + (lane & 31);
+    const int kh = 8 * (lane >> 5);  // this lane's k' offset inside a chunk
+
+    // phasor operand: chunk q < HC holds Re A at f = 16 q + kh + t, chunk
+    // q + HC holds -Im A at the same f
+    V ah[NC], al[NC];
+    {
+        const double u = (i - a.n_l / 2) * a.du;
+        const bool row_ok = i < a.n_l;
+#pragma unroll
+        for (int qq = 0; qq < HC; ++qq) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int f = 16 * qq + kh + t;
+                float cr = 0.f, ci = 0.f;
+                if (row_ok && f < a.n_f) {
+                    const float2 e = cis(kp[static_cast<size_t>(kap) * a.n_f + f] * u);
+                    cr = e.x;
+                    ci = -e.y;
+                }
+                const T crh = static_cast<T>(cr), cih = static_cast<T>(ci);
+                ah[qq][t] = crh;
+                al[qq][t] = static_cast<T>(cr - static_cast<float>(crh));
+                ah[qq + HC][t] = cih;
+                al[qq + HC][t] = static_cast<T>(ci - static_cast<float>(cih));
+            }
+        }
+    }
+
+    const int n_ct = a.n_chp / 32;
+    for (int ct = 0; ct < n_ct; ++ct) {
+        const int c = ct * 32 + (lane & 31);
+        const u32x4* base = reinterpret_cast<const u32x4*>(cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp);
+        const int stride4 = a.n_fp / 8;  // u32x4 per part
+        f32x16 accr = {}, acci = {};
+#pragma unroll
+        for (int qq = 0; qq < NC; ++qq) {
+            const bool second = qq >= HC;
+            const int f0 = 16 * (second ? qq - HC : qq) + kh;
+            const u32x4 rh = base[0 * stride4 + f0 / 8], rl = base[1 * stride4 + f0 / 8];
+            const u32x4 ih = base[2 * stride4 + f0 / 8], il = base[3 * stride4 + f0 / 8];
+            // Re Q: B' = [Re C; Im C];  Im Q: B'' = [Im C; -Re C]
+            const u32x4 b1h = second ? ih : rh, b1l = second ? il : rl;
+            const u32x4 b2h = second ? neg16(rh) : ih, b2l = second ? neg16(rl) : il;
+            const V vb1h = __builtin_bit_cast(V, b1h), vb1l = __builtin_bit_cast(V, b1l);
+            const V vb2h = __builtin_bit_cast(V, b2h), vb2l = __builtin_bit_cast(V, b2l);
+            accr = Half<F16>::mfma(ah[qq], vb1h, accr);
+            accr = Half<F16>::mfma(ah[qq], vb1l, accr);
+            accr = Half<F16>::mfma(al[qq], vb1h, accr);
+            acci = Half<F16>::mfma(ah[qq], vb2h, acci);
+            acci = Half<F16>::mfma(ah[qq], vb2l, acci);
+            acci = Half<F16>::mfma(al[qq], vb2h, acci);
+        }
+        if (c < a.n_ch) {
+            const float sc = ldexpf(1.f, -se[static_cast<size_t>(kap) * a.n_chp + c]);
+            float2* dst = q + (static_cast<size_t>(c) * a.n_z + kap) * a.n_l;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
+                if (r < a.n_l) dst[r] = make_float2(accr[v] * sc, acci[v] * sc);
+            }
+        }
+    }
+}
+
+template <bool F16>
+int run_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
+    typedef typename Half<F16>::T T;
+    MfmaArgs a{};
+    a.n_ch = p.n_ch;
+    a.n_chp = p.n_chp;
+    a.n_z = p.n_z;
+    a.n_f = p.n_f;
+    a.n_fp = p.n_fp;
+    a.n_l = p.n_l;
+    a.du = p.du;
+    T* cs = reinterpret_cast<T*>(ws + p.off_mfma_b);
+    int* se = reinterpret_cast<int*>(ws + p.off_mfma_a);
+    const long long waves = static_cast<long long>(p.n_z) * p.n_chp;
+    hipLaunchKernelGGL(strengths_kernel<F16>, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, s, spec,
+                       reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<const double*>(ws + p.off_kp),
+                       reinterpret_cast<const float*>(ws + p.off_wk), a, cs, se);
+    int rc = check_launch("range compression (strengths)");
+    if (rc) return rc;
+    const long long blocks = static_cast<long long>(p.n_z) * ((p.n_l + 127) / 128);
+    const double* kp = reinterpret_cast<const double*>(ws + p.off_kp);
+    switch (p.n_fp / 8) {
+#define PL_NC(N)                                                                                          \
+    case N:                                                                                               \
+        hipLaunchKernelGGL((range_mfma_kernel<F16, N>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
+                           kp, a, q);                                                                     \
+        break;
+        PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
+#undef PL_NC
+        default:
+            return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
+    }
+    return check_launch("range compression (MFMA)");
+}
+
+}  // namespace
+
+int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
+    if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
+    return p.precision == PL_PREC_FP16 ? run_mfma<true>(p, spec, ws, q, s) : run_mfma<false>(p, spec, ws, q, s);
 }
 
 }  // namespace pl

@@ -219,8 +219,17 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_deap = take(static_cast<size_t>(p.n_l) * 4);
     p.off_kp = take(nz * nf * 8);
     p.off_wk = take(nz * nf * 4);
-    p.off_mfma_a = off;
-    p.off_mfma_b = off;
+    p.n_chp = (p.n_ch + 31) / 32 * 32;
+    p.n_fp = (p.n_f + 15) / 16 * 16;
+    if (p.precision != PL_PREC_FP32) {
+        if (p.n_fp > 128)
+            return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
+        p.off_mfma_a = take(nz * static_cast<size_t>(p.n_chp) * 4);
+        p.off_mfma_b = take(nz * static_cast<size_t>(p.n_chp) * 4 * p.n_fp * 2);
+    } else {
+        p.off_mfma_a = off;
+        p.off_mfma_b = off;
+    }
     p.total = off;
     *out = p;
     return PL_OK;
