@@ -97,6 +97,8 @@ def main() -> int:
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -111,6 +113,15 @@ def main() -> int:
         print("bench.py needs a GPU", flush=True)
         return 1
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return 0
     wl = W.WORKLOADS[args.config]
     a = wl.array
     log(f"[bench] {args.config}: {describe(wl)}")

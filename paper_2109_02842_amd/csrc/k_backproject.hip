@@ -31,8 +31,19 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // gfx9 raw-buffer descriptor word 3: 32-bit data format, no swizzle
 constexpr int kBufferFlags = 0x00020000;
 
+// Buffer descriptor of a wavefront-uniform slab.  The address halves go
+// through readfirstlane so the compiler knows the descriptor is uniform and
+// emits plain scalar-descriptor loads (no waterfall loops).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(const float2* p, unsigned bytes) {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    void* u = reinterpret_cast<void*>((static_cast<unsigned long long>(hi) << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, 0, __builtin_amdgcn_readfirstlane(bytes), kBufferFlags);
+}
+
 __device__ __forceinline__ float2 load_c64(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, __builtin_amdgcn_readfirstlane(soff), 0);
     return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
 }
 
@@ -101,9 +112,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
 #define PL_STAGE(C_, BUF_)                                                                    \
     {                                                                                         \
         const int s0_ = __builtin_amdgcn_readfirstlane(win[C_]);                              \
-        const __amdgpu_buffer_rsrc_t rs_ = __builtin_amdgcn_make_buffer_rsrc(                 \
-            const_cast<float2*>(q + static_cast<size_t>(C_) * a.n_z * a.n_l), 0, slab_bytes, \
-            kBufferFlags);                                                                    \
+        const __amdgpu_buffer_rsrc_t rs_ =                                                    \
+            slab_rsrc(q + static_cast<size_t>(C_) * a.n_z * a.n_l, slab_bytes);               \
         const unsigned v0_ = static_cast<unsigned>(s0_ + ie0) * 8u;                           \
         const unsigned v1_ = static_cast<unsigned>(s0_ + ie1) * 8u;                           \
         float2* dst_ = qbuf + (BUF_) * buf_stride + wave * RPW * a.wpad;                      \
