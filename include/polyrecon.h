@@ -189,8 +189,17 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 wavenumber, so this also sets the range-grid step.
  *   waves         wavefronts per back-projection workgroup: 0 = automatic, or
  *                 4, 8 (8 only with the 8x8 tile).
- * tile, kz_per_lane and waves are tuning knobs; results agree to the method's
- * tolerance whatever their values.
+ *   mfma_backprojection  BF16 / FP16 modes only: 1 = back-project on the
+ *                 matrix cores (PL_EUNSUPPORTED if the grid does not allow it);
+ *                 0 (automatic) and -1 use the VALU back-projection.
+ *                 The MFMA back-projection keeps the range profiles as BF16
+ *                 hi + lo parts, forms each 4x4 pixel group's interpolation x
+ *                 carrier operand over a 16-sample range window, and runs
+ *                 three split products per pair with FP32 accumulation.  It
+ *                 needs the group's taps inside 16 samples; when the requested
+ *                 oversampling makes them wider the plan lowers it (not below 4).
+ * tile, kz_per_lane and waves are tuning knobs (FP32 back-projection); results
+ * agree to the method's tolerance whatever their values.
  */
 typedef struct pl_hybrid_opts {
     int32_t precision;
@@ -200,7 +209,7 @@ typedef struct pl_hybrid_opts {
     int32_t tile;
     int32_t kz_per_lane;
     int32_t waves;
-    int32_t reserved;
+    int32_t mfma_backprojection;
 } pl_hybrid_opts;
 
 /* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */
@@ -214,7 +223,7 @@ typedef struct pl_hybrid_plan_info {
     int32_t window;      /* range samples staged per pixel tile and channel      */
     int32_t tile_x;      /* back-projection pixel tile                           */
     int32_t tile_y;
-    int32_t reserved;
+    int32_t mfma_backprojection; /* 1 if the back-projection runs on the matrix cores */
     double du;           /* range-grid step (m of rho_T + rho_R)                 */
     double beta;         /* exponential-of-semicircle kernel shape               */
     size_t workspace_bytes;
@@ -273,7 +282,10 @@ int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid
 /* ------------------------------------------------- the hybrid steps alone */
 /*
  * The four steps of reconstruct_hybrid as separate calls, for inspection and
- * step-level checks.  They use the same plan; buffers are device memory:
+ * step-level checks.  They exchange complex64 range profiles, so they plan as
+ * with opts->mfma_backprojection = -1 (the plan hybrid_plan_info reports for
+ * those options) and return PL_EUNSUPPORTED if it is 1.  Buffers are device
+ * memory:
  *   scan_fft:        echo [c][m][f] -> spec [c][kz][f]        (eq. 2/12)
  *   range_compress:  spec [c][kz][f] -> q [c][kz][n_l]        (eq. 8a/19a)
  *       q[c][kz][i] approximates sum_f w_f k_f S e^{j k'_f l_i} with

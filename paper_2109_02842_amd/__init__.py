@@ -58,14 +58,14 @@ class ImageGridC(C.Structure):
 class HybridOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("interp", C.c_int32), ("l_oversample", C.c_double),
                 ("nufft_tol", C.c_double), ("tile", C.c_int32), ("kz_per_lane", C.c_int32),
-                ("waves", C.c_int32), ("reserved", C.c_int32)]
+                ("waves", C.c_int32), ("mfma_backprojection", C.c_int32)]
 
 
 class HybridPlanInfo(C.Structure):
     _fields_ = [("n_kz", C.c_int32), ("n_l", C.c_int32), ("n_fine", C.c_int32),
                 ("kernel_width", C.c_int32), ("n_blocks", C.c_int32), ("block", C.c_int32),
                 ("window", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("reserved", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
+                ("mfma_backprojection", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
                 ("workspace_bytes", C.c_size_t)]
 
 
@@ -202,13 +202,13 @@ def _grid(grid) -> ImageGridC:
 
 
 def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
-          waves=0) -> HybridOpts:
+          waves=0, mfma_backprojection=0) -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {list(INTERPS)}")
     return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol),
-                      int(tile), int(kz_per_lane), int(waves), 0)
+                      int(tile), int(kz_per_lane), int(waves), int(mfma_backprojection))
 
 
 def check_sampling(geom: Geometry, grid) -> int:
@@ -231,6 +231,7 @@ class PlanInfo:
     beta: float
     workspace_bytes: int
     k_ref: list
+    mfma_backprojection: bool = False
 
 
 def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
@@ -240,7 +241,7 @@ def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
                                   C.byref(info), C.cast(kref, _P)))
     return PlanInfo(info.n_kz, info.n_l, info.n_fine, info.kernel_width, info.n_blocks, info.block,
                     info.window, (info.tile_x, info.tile_y), info.du, info.beta,
-                    int(info.workspace_bytes), list(kref[: info.n_blocks]))
+                    int(info.workspace_bytes), list(kref[: info.n_blocks]), bool(info.mfma_backprojection))
 
 
 def hybrid_workspace_bytes(geom: Geometry, grid, **opts) -> int:
@@ -360,10 +361,20 @@ def scan_fft(geom: Geometry, echo, out=None):
     return out
 
 
+def _stage_opts(opts: dict) -> dict:
+    """Options of a single-stage call: complex64 profiles, so the plan never
+    takes the matrix-core back-projection."""
+    if opts.get("mfma_backprojection", 0) > 0:
+        raise ValueError("the MFMA back-projection runs only inside reconstruct_hybrid")
+    return dict(opts, mfma_backprojection=-1)
+
+
 def range_compress(geom: Geometry, grid, spec, out=None, ws=None, **opts):
-    """Range profiles q[c][kz][n_l] and the range-grid origins l_lo[c] (numpy)."""
+    """Range profiles q[c][kz][n_l] and the range-grid origins l_lo[c] (numpy).
+    The plan is that of hybrid_plan_info(..., mfma_backprojection=-1)."""
     import numpy as np
     torch = _torch()
+    opts = _stage_opts(opts)
     pi = hybrid_plan_info(geom, grid, **opts)
     ws = _ws(ws, pi.workspace_bytes)
     shape = (geom.n_channels, geom.n_scan, pi.n_l)
@@ -377,8 +388,10 @@ def range_compress(geom: Geometry, grid, spec, out=None, ws=None, **opts):
 
 
 def backproject(geom: Geometry, grid, q, out=None, ws=None, **opts):
-    """Spectrum G[p][kz] (p = iy*nx + ix) from range profiles, eq. (8b)/(19b)."""
+    """Spectrum G[p][kz] (p = iy*nx + ix) from range profiles, eq. (8b)/(19b).
+    The plan is that of hybrid_plan_info(..., mfma_backprojection=-1)."""
     torch = _torch()
+    opts = _stage_opts(opts)
     pi = hybrid_plan_info(geom, grid, **opts)
     ws = _ws(ws, pi.workspace_bytes)
     shape = (grid.ny * grid.nx, geom.n_scan)

@@ -10,9 +10,19 @@ namespace {
 
 bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
+// stage: the single-stage entry points exchange complex64 range profiles,
+// which only the VALU back-projection reads; they plan without the
+// matrix-core back-projection.
 int prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws, size_t ws_bytes,
-            HybridPlan* p, DeviceTables* dt, const char* what) {
-    int rc = make_plan(g, grid, opts, p);
+            HybridPlan* p, DeviceTables* dt, const char* what, bool stage = false) {
+    pl_hybrid_opts o{};
+    if (opts) o = *opts;
+    if (stage) {
+        if (o.mfma_backprojection > 0)
+            return fail(PL_EUNSUPPORTED, "%s: the MFMA back-projection runs only inside reconstruct_hybrid", what);
+        o.mfma_backprojection = -1;
+    }
+    int rc = make_plan(g, grid, (opts || stage) ? &o : nullptr, p);
     if (rc) return rc;
     if (!ws) return fail(PL_EWORKSPACE, "%s: null workspace", what);
     if (!aligned256(ws)) return fail(PL_EWORKSPACE, "%s: workspace must be 256-byte aligned", what);
@@ -70,7 +80,7 @@ int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     info->window = p.window;
     info->tile_x = p.tile_x;
     info->tile_y = p.tile_y;
-    info->reserved = 0;
+    info->mfma_backprojection = p.bp_mfma ? 1 : 0;
     info->du = p.du;
     info->beta = p.beta;
     info->workspace_bytes = p.total;
@@ -123,7 +133,7 @@ int range_compress(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     if (!spec || !q) return fail(PL_EINVAL, "range_compress: null pointer");
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "range_compress");
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "range_compress", true);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
@@ -147,7 +157,7 @@ int backproject(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid
     if (!q || !spectrum) return fail(PL_EINVAL, "backproject: null pointer");
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "backproject");
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "backproject", true);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
@@ -195,10 +205,17 @@ int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, c
         (rc = launch_scan_fft(g, reinterpret_cast<const float2*>(echo), spec, tw_scan, p.scan_rad, stream)))
         return rc;
     if ((rc = mark(2))) return rc;
-    rc = p.precision == PL_PREC_FP32 ? launch_range_compress_fp32(p, spec, w, q, stream)
-                                     : launch_range_compress_mfma(p, spec, w, q, stream);
-    if (rc) return rc;
-    if ((rc = mark(3)) || (rc = launch_backproject(p, dt, q, w, G, stream))) return rc;
+    if (p.bp_mfma) {
+        // split BF16 profiles in the same bytes as the complex64 ones
+        unsigned short* qs = reinterpret_cast<unsigned short*>(w + p.off_q);
+        if ((rc = launch_range_compress_mfma_split(p, spec, w, qs, stream))) return rc;
+        if ((rc = mark(3)) || (rc = launch_backproject_mfma(p, dt, qs, w, G, stream))) return rc;
+    } else {
+        rc = p.precision == PL_PREC_FP32 ? launch_range_compress_fp32(p, spec, w, q, stream)
+                                         : launch_range_compress_mfma(p, spec, w, q, stream);
+        if (rc) return rc;
+        if ((rc = mark(3)) || (rc = launch_backproject(p, dt, q, w, G, stream))) return rc;
+    }
     if ((rc = mark(4)) || (rc = launch_kz_ifft(p, G, reinterpret_cast<float2*>(image), tw_scan, stream))) return rc;
     return mark(5);
 }

@@ -77,7 +77,9 @@ struct HybridPlan {
     double x0 = 0, y0 = 0, dx = 0, dy = 0;
     int precision = PL_PREC_FP32, interp = PL_INTERP_BSPLINE4;
     double sigma_l = 8.0, tol = 1e-6;
-    int force_tile = 0, force_kpl = 0, force_waves = 0;
+    int force_tile = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0;
+    bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
+    double half_band = 0, sigma_used = 0;
     // range grid and NUFFT
     int n_l = 0, n_fine = 0, W = 0;
     double du = 0, h = 0, beta = 0;
@@ -109,8 +111,12 @@ int launch_range_compress_fp32(const HybridPlan& p, const float2* spec, char* ws
                                hipStream_t s);
 int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q,
                                hipStream_t s);
+int launch_range_compress_mfma_split(const HybridPlan& p, const float2* spec, char* ws,
+                                     unsigned short* qs, hipStream_t s);
 int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws,
                        float2* G, hipStream_t s);
+int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs,
+                            char* ws, float2* G, hipStream_t s);
 int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw,
                    hipStream_t s);
 int launch_simulate(const pl_geometry* g, const DeviceTables& dt, int n_scat, const double* xyz,

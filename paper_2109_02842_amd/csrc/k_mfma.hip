@@ -102,14 +102,21 @@ __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict
 
 __device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
 
+__device__ __forceinline__ unsigned short bf16_of(float x) {
+    return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
+}
+
 // One block = one k_z bin x 128 range samples; wavefront w owns rows
 // [32 w, 32 w + 32) of that range block and keeps its phasor operand A' for
 // all of K' in registers, then walks the channel tiles of 32.
-template <bool F16, int NCH>
+// SPLIT: instead of complex64 profiles, write four BF16 planes per
+// (channel, k_z) -- Re hi, Re lo, Im hi, Im lo with x = hi + lo -- the
+// operand layout of the matrix-core back-projection.
+template <bool F16, int NCH, bool SPLIT>
 __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16>::T* __restrict__ cs,
                                                          const int* __restrict__ se,
                                                          const double* __restrict__ kp, MfmaArgs a,
-                                                         float2* __restrict__ q) {
+                                                         void* __restrict__ qout) {
     typedef typename Half<F16>::T T;
     typedef typename Half<F16>::V V;
     constexpr int NC = NCH;          // chunks of 16 in K' = 2 n_fp, NC = n_fp / 8
@@ -175,18 +182,35 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
         }
         if (c < a.n_ch) {
             const float sc = ldexpf(1.f, -se[static_cast<size_t>(kap) * a.n_chp + c]);
-            float2* dst = q + (static_cast<size_t>(c) * a.n_z + kap) * a.n_l;
+            if constexpr (SPLIT) {
+                unsigned short* dst =
+                    static_cast<unsigned short*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 4 * a.n_l;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
-                if (r < a.n_l) dst[r] = make_float2(accr[v] * sc, acci[v] * sc);
+                for (int v = 0; v < 16; ++v) {
+                    const int r = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
+                    if (r < a.n_l) {
+                        const float xr = accr[v] * sc, xi = acci[v] * sc;
+                        const unsigned short rh = bf16_of(xr), ih = bf16_of(xi);
+                        dst[r] = rh;
+                        dst[a.n_l + r] = bf16_of(xr - __uint_as_float(static_cast<unsigned>(rh) << 16));
+                        dst[2 * a.n_l + r] = ih;
+                        dst[3 * a.n_l + r] = bf16_of(xi - __uint_as_float(static_cast<unsigned>(ih) << 16));
+                    }
+                }
+            } else {
+                float2* dst = static_cast<float2*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * a.n_l;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int r = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
+                    if (r < a.n_l) dst[r] = make_float2(accr[v] * sc, acci[v] * sc);
+                }
             }
         }
     }
 }
 
-template <bool F16>
-int run_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
+template <bool F16, bool SPLIT>
+int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStream_t s) {
     typedef typename Half<F16>::T T;
     MfmaArgs a{};
     a.n_ch = p.n_ch;
@@ -209,7 +233,7 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipSt
     switch (p.n_fp / 8) {
 #define PL_NC(N)                                                                                          \
     case N:                                                                                               \
-        hipLaunchKernelGGL((range_mfma_kernel<F16, N>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
+        hipLaunchKernelGGL((range_mfma_kernel<F16, N, SPLIT>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
                            kp, a, q);                                                                     \
         break;
         PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
@@ -224,7 +248,13 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipSt
 
 int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
     if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
-    return p.precision == PL_PREC_FP16 ? run_mfma<true>(p, spec, ws, q, s) : run_mfma<false>(p, spec, ws, q, s);
+    return p.precision == PL_PREC_FP16 ? run_mfma<true, false>(p, spec, ws, q, s) : run_mfma<false, false>(p, spec, ws, q, s);
+}
+
+int launch_range_compress_mfma_split(const HybridPlan& p, const float2* spec, char* ws, unsigned short* qs,
+                                     hipStream_t s) {
+    if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
+    return p.precision == PL_PREC_FP16 ? run_mfma<true, true>(p, spec, ws, qs, s) : run_mfma<false, true>(p, spec, ws, qs, s);
 }
 
 }  // namespace pl

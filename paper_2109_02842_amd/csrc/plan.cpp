@@ -70,6 +70,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.force_tile = opts->tile;
         p.force_kpl = opts->kz_per_lane;
         p.force_waves = opts->waves;
+        p.force_bp_mfma = opts->mfma_backprojection;
     }
     if (p.force_kpl != 0 && p.force_kpl != 1 && p.force_kpl != 2 && p.force_kpl != 4)
         return fail(PL_EINVAL, "kz_per_lane must be 0, 1, 2 or 4");
@@ -91,35 +92,75 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // One reference wavenumber per block of k_z bins: the centre of the band
     // of k_rho it spans.  The reference cancels exactly between eqs. (8a) and
     // (8b); only the bandwidth of the range profiles depends on it.
-    // One k_z bin per lane by default: measured fastest on gfx950, since more
-    // bins per lane make the staged window too large for several resident
-    // workgroups per CU.
-    const int kpl = p.force_kpl ? p.force_kpl : 1;
-    p.block = kLanes * kpl;
-    p.n_blocks = (p.n_z + p.block - 1) / p.block;
-    double half_band = 0.0;
-    for (int b = 0; b < p.n_blocks; ++b) {
-        double lo = 1e300, hi = -1e300;
-        for (int kap = b * p.block; kap < std::min(p.n_z, (b + 1) * p.block); ++kap) {
-            const int sk = kap < (p.n_z + 1) / 2 ? kap : kap - p.n_z;
-            const double kz = 2.0 * kPi * sk / (p.n_z * g->scan_step);
-            for (int f = 0; f < p.n_f; ++f) {
-                const double arg = g->k[f] * g->k[f] - 0.25 * kz * kz;
-                if (arg <= 0) continue;
-                const double kr = std::sqrt(arg);
-                lo = std::min(lo, kr);
-                hi = std::max(hi, kr);
+    // Reference wavenumber of every k_z block and the range-grid step for a
+    // given block size.
+    auto set_blocks = [&](int block, double sigma) {
+        p.block = block;
+        p.n_blocks = (p.n_z + p.block - 1) / p.block;
+        double half_band = 0.0;
+        for (int b = 0; b < p.n_blocks; ++b) {
+            double lo = 1e300, hi = -1e300;
+            for (int kap = b * p.block; kap < std::min(p.n_z, (b + 1) * p.block); ++kap) {
+                const int sk = kap < (p.n_z + 1) / 2 ? kap : kap - p.n_z;
+                const double kz = 2.0 * kPi * sk / (p.n_z * g->scan_step);
+                for (int f = 0; f < p.n_f; ++f) {
+                    const double arg = g->k[f] * g->k[f] - 0.25 * kz * kz;
+                    if (arg <= 0) continue;
+                    const double kr = std::sqrt(arg);
+                    lo = std::min(lo, kr);
+                    hi = std::max(hi, kr);
+                }
+            }
+            if (hi < lo) {
+                p.kref[b] = 0.0;
+            } else {
+                p.kref[b] = 0.5 * (lo + hi);
+                half_band = std::max(half_band, 0.5 * (hi - lo));
             }
         }
-        if (hi < lo) {
-            p.kref[b] = 0.0;
-        } else {
-            p.kref[b] = 0.5 * (lo + hi);
-            half_band = std::max(half_band, 0.5 * (hi - lo));
+        if (half_band <= 0) half_band = 1.0;  // single frequency, no k_z spread
+        p.half_band = half_band;
+        p.sigma_used = sigma;
+        p.du = kPi / (sigma * half_band);
+    };
+
+    // MFMA back-projection (BF16 / FP16 modes): 8x8 tiles of four 4x4 pixel
+    // groups, each group's taps inside one 16-sample window.  |l(p) - l(q)| <=
+    // 2 |p - q|, so a group spans at most 2 * diagonal / du samples plus the
+    // 4 taps and one sample each for flooring and even alignment.
+    p.bp_mfma = false;
+    if (p.precision != PL_PREC_FP32 && p.force_bp_mfma > 0 && p.force_kpl == 0 && p.force_tile == 0 &&
+        p.force_waves == 0) {
+        const int kb = std::min(256, (p.n_z + 63) / 64 * 64);
+        const double gdiag = std::hypot(3.0 * grid->dx, 3.0 * grid->dy);
+        set_blocks(kb, p.sigma_l);
+        if (std::ceil(2.0 * gdiag / p.du) + 6 > 16) {
+            // widest grid step that fits, as long as the oversampling stays >= 4
+            const double du_fit = 2.0 * gdiag / 9.999;
+            const double sigma_fit = kPi / (du_fit * p.half_band);
+            if (sigma_fit >= 4.0) set_blocks(kb, std::min(p.sigma_l, sigma_fit));
+        }
+        const double rt = 0.5 * std::hypot(7.0 * grid->dx, 7.0 * grid->dy);
+        int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7;
+        wl = std::max(16, wl + (wl & 1));
+        const size_t lds = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * kb * (2 * wl + 1) * 4;
+        if (std::ceil(2.0 * gdiag / p.du) + 6 <= 16 && wl <= 64 && lds <= kMaxLds && p.n_f <= 128) {
+            p.bp_mfma = true;
+            p.tile_x = p.tile_y = 8;
+            p.window = wl;
+            p.window_pad = 2 * wl + 1;  // LDS row stride in dwords: 4 parts x wl bf16 + 1
+            p.waves = 4;
         }
     }
-    if (half_band <= 0) half_band = 1.0;  // single frequency, no k_z spread
-    p.du = kPi / (p.sigma_l * half_band);
+    if (p.force_bp_mfma > 0 && !p.bp_mfma)
+        return fail(PL_EUNSUPPORTED, "the MFMA back-projection does not fit this grid (BF16/FP16 only)");
+    if (!p.bp_mfma) {
+        // One k_z bin per lane by default: measured fastest on gfx950, since
+        // more bins per lane make the staged window too large for several
+        // resident workgroups per CU.
+        const int kpl = p.force_kpl ? p.force_kpl : 1;
+        set_blocks(kLanes * kpl, p.sigma_l);
+    }
 
     // Range window of every channel over the pixel-centre rectangle.
     const double gx1 = grid->x0 + (grid->nx - 1) * grid->dx, gy1 = grid->y0 + (grid->ny - 1) * grid->dy;
@@ -138,6 +179,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
 
     // Back-projection tile: the staged range window must hold every tap of
     // the tile's pixels.  |l(p) - l(centre)| <= 2 * half-diagonal.
+    if (!p.bp_mfma) {
     // Prefer the largest tile whose window fits 64 samples (one staging load
     // per lane and row; the 2x2 fallback allows 128) and whose LDS (window
     // starts + two staged windows of 64 x kz_per_lane rows) fits the
@@ -161,9 +203,10 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         return fail(PL_EUNSUPPORTED, "8 wavefronts per workgroup need the 8x8 tile");
     if (backproject_lds_bytes(p.n_ch, p.block, p.window | 1) > kMaxLds)
         return fail(PL_EUNSUPPORTED, "back-projection staging exceeds the LDS (lower kz_per_lane)");
+    }
     if (p.window > 128)
         return fail(PL_EUNSUPPORTED, "pixels are too coarse for the range grid (window %d > 128)", p.window);
-    p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes
+    if (!p.bp_mfma) p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes
     p.tiles_x = (grid->nx + p.tile_x - 1) / p.tile_x;
     p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
 

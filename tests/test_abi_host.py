@@ -155,3 +155,38 @@ def test_raw_abi_argument_errors_before_device_use():
     assert L.simulate_echo(g.handle, -1, fake, fake, fake, None) == pr.PL_EINVAL
     assert L.simulate_echo(g.handle, 3, None, fake, fake, None) == pr.PL_EINVAL
     assert L.scan_fft(None, fake, fake, None) == pr.PL_EINVAL
+
+
+def _fine_grid(nx, ny, d):
+    return W.ImageGrid(nx=nx, ny=ny, x0=-d * (nx - 1) / 2 + 0.004, y0=-d * (ny - 1) / 2 - 0.003, dx=d, dy=d)
+
+
+def test_mfma_backprojection_plan_rules():
+    g = pr.make_geometry(W.C1.array)
+    fine = _fine_grid(40, 40, 0.0015)
+    p = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1)
+    assert p.mfma_backprojection and p.tile == (8, 8) and p.block % 64 == 0 and p.window % 2 == 0
+    # every 4x4 group's taps fit 16 samples: 2 x group diagonal / du + 6 <= 16
+    assert math.ceil(2 * math.hypot(3 * fine.dx, 3 * fine.dy) / p.du) + 6 <= 16
+    assert not pr.hybrid_plan_info(g, fine, precision="fp32").mfma_backprojection
+    q = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=-1)
+    assert not q.mfma_backprojection and q.block == 64
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="fp32", mfma_backprojection=1)
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(pr.PolyreconError):
+        pr.hybrid_plan_info(g, W.C1.grid, precision="bf16", mfma_backprojection=1)   # pixels too coarse
+    assert not pr.hybrid_plan_info(g, fine, precision="bf16").mfma_backprojection   # opt-in
+    # the full-size workloads allow it in the BF16 / FP16 modes
+    for wl in (W.C2, W.C3):
+        assert pr.hybrid_plan_info(pr.make_geometry(wl.array), wl.grid, precision="fp16",
+                                   mfma_backprojection=1).mfma_backprojection
+    # the single-stage calls exchange complex64 profiles
+    with pytest.raises(ValueError):
+        pr.range_compress(g, fine, None, precision="bf16", mfma_backprojection=1)
+    import ctypes as C
+    fake = C.c_void_p(1 << 20)
+    opts = pr._opts(precision="bf16", mfma_backprojection=1)
+    assert pr.lib().range_compress(g.handle, C.byref(pr._grid(fine)), C.byref(opts), fake, fake, None, fake,
+                                   1 << 40, None) == pr.PL_EUNSUPPORTED
+    assert "reconstruct_hybrid" in pr.last_error()

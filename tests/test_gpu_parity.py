@@ -165,7 +165,7 @@ def test_range_compress_matches_direct_nudft(interp, wlname):
 def test_mfma_range_compress_matches_direct_nudft(precision, wlname):
     wl = {"tiny-mono": W.tiny("mono"), "multi-small": multi_small(), "C1": W.C1}[wlname]
     g = pr.make_geometry(wl.array)
-    plan = pr.hybrid_plan_info(g, wl.grid, precision=precision)
+    plan = pr.hybrid_plan_info(g, wl.grid, precision=precision, mfma_backprojection=-1)
     s = W.random_echo(wl.array, 9)
     say("mfma range_compress", wlname, precision)
     spec = pr.scan_fft(g, dev(s))
@@ -196,6 +196,39 @@ def test_hybrid_mfma_end_to_end_small(precision, wlname):
     err = rel(img, ohyb.image(arr, wl.grid, s))
     say("hybrid", precision, wlname, "rel L2", err)
     assert err < 1e-3
+
+
+def _fine_grid(nx, ny, d):
+    """Off-centre ragged grid of d-spaced pixels (fine enough for the
+    matrix-core back-projection's 16-sample pixel groups)."""
+    return W.ImageGrid(nx=nx, ny=ny, x0=-d * (nx - 1) / 2 + 0.004, y0=-d * (ny - 1) / 2 - 0.003, dx=d, dy=d)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("interp", ["bspline4", "lagrange4", "linear"])
+@pytest.mark.parametrize("case", ["tiny-multi", "multi-small", "C1"])
+def test_mfma_backprojection_matches_oracle(case, interp, precision):
+    wl = {"tiny-multi": W.tiny("multi"), "multi-small": multi_small(), "C1": W.C1}[case]
+    grid = {"tiny-multi": _fine_grid(21, 11, 0.0015), "multi-small": _fine_grid(27, 35, 0.0015),
+            "C1": _fine_grid(44, 37, 0.0015)}[case]
+    sigma = 16.0 if interp == "lagrange4" else 8.0
+    g = pr.make_geometry(wl.array)
+    plan = pr.hybrid_plan_info(g, grid, precision=precision, interp=interp, l_oversample=sigma)
+    assert plan.mfma_backprojection and plan.tile == (8, 8) and plan.block % 64 == 0
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 41)
+    say("mfma backprojection", case, interp, precision, "window", plan.window, "block", plan.block)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), precision=precision, interp=interp,
+                                     l_oversample=sigma, mfma_backprojection=1))
+    ref = ohyb.image(arr, grid, s)
+    err = rel(img, ref)
+    valu = host(pr.reconstruct_hybrid(g, grid, dev(s), precision=precision, interp=interp,
+                                      l_oversample=sigma, mfma_backprojection=-1))
+    err_valu = rel(valu, ref)
+    say("   rel L2", err, "VALU back-projection", err_valu)
+    # linear taps carry their own interpolation error; the matrix cores must
+    # not add to it beyond the split-BF16 rounding
+    assert err < (1e-3 if interp != "linear" else 1.2 * err_valu + 1e-3)
 
 
 @pytest.mark.parametrize("wlname", ["tiny-mono", "tiny-multi", "multi-small", "C1"])
@@ -267,8 +300,9 @@ def _spectrum_subset(img, kappas, pix):
     return G[np.ix_(kappas, pix)]
 
 
-@pytest.mark.parametrize("wl,precision", [(W.C2, "fp32"), (W.C3, "fp32"), (W.C2, "bf16"), (W.C2, "fp16")],
-                         ids=["C2-fp32", "C3-fp32", "C2-bf16", "C2-fp16"])
+@pytest.mark.parametrize("wl,precision", [(W.C2, "fp32"), (W.C3, "fp32"), (W.C2, "bf16"), (W.C2, "fp16"),
+                                         (W.C3, "bf16")],
+                         ids=["C2-fp32", "C3-fp32", "C2-bf16", "C2-fp16", "C3-bf16"])
 def test_hybrid_full_size_sampled(wl, precision):
     # The full workload in the launch configuration the benchmark times;
     # the oracle evaluates sampled (k_z, pixel) pairs of the spectrum.
