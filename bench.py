@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "reconstructed voxels/sec, hybrid-NUFFT vs BP, FP32 vs BF16-MFMA at stated err"
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0               # MI355X published HBM3E bandwidth
+BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
 
 
@@ -95,6 +96,10 @@ def main() -> int:
     ap.add_argument("--l-oversample", type=float, default=8.0)
     ap.add_argument("--kz-per-lane", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1],
+                    help="1: back-projection on the matrix cores (BF16/FP16 modes)")
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--kz-block", type=int, default=0)
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -130,7 +135,8 @@ def main() -> int:
     echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
     torch.cuda.synchronize()
     opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
-                l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves)
+                l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves,
+                mfma_backprojection=args.mfma_bp, tile_y=args.tile_y, kz_block=args.kz_block)
     plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
     img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
     log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
@@ -191,6 +197,15 @@ def main() -> int:
     terms = a.n_scan * wl.grid.nx * wl.grid.ny * geom.n_channels
     bp_ms = stage["backproject"]
     achieved = FLOP_PER_TERM * terms / (bp_ms * 1e-3) / 1e12
+    if plan.mfma_backprojection:
+        # algorithmic flops against the dense BF16 matrix-core peak; the
+        # kernel issues 6 MFMA 16x16x32 per (4x4 pixels, 16 k_z, channel)
+        roof = {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
+                "issued_tflops": 6 * 2 * 16 * 16 * 32 / 256 * terms / (bp_ms * 1e-3) / 1e12}
+    else:
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS}
     out = {
         "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -199,10 +214,8 @@ def main() -> int:
         "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
                    "tile": list(plan.tile), "kz_block": plan.block},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "backproject", "flop_per_launch": FLOP_PER_TERM * terms,
-                     "avg_launch_ms": bp_ms},
+        "roofline": dict(roof, unit="TFLOP/s", traffic=None, kernel="backproject",
+                         flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
         "stages_ms": stage,
         "plan_build_ms": first_ms,
     }
@@ -212,18 +225,21 @@ def main() -> int:
         log(f"[bench] {args.precision}: rel L2 vs oracle {err:.2e} ({sample})")
     if not args.no_variants:
         out["variants"] = {}
-        for prec in ("bf16", "fp16", "fp32"):
-            if prec == args.precision:
+        for name, prec, mbp in (("bf16", "bf16", 0), ("fp16", "fp16", 0), ("fp32", "fp32", 0),
+                                ("bf16-mfma-bp", "bf16", 1), ("fp16-mfma-bp", "fp16", 1)):
+            if prec == args.precision and mbp == args.mfma_bp:
                 continue
-            vopts = dict(opts, precision=prec)
+            vopts = dict(opts, precision=prec, mfma_backprojection=mbp)
+            if mbp:
+                vopts.update(tile=0, tile_y=0, kz_block=0, kz_per_lane=0, waves=0)
             vms, vstage, _, vmed, _ = time_path(vopts, args.steps, 1)
             v = {"value": voxels / (vms * 1e-3), "ms_per_step": vms, "stages_ms": vstage,
                  "speedup_vs_main": ms / vms}
             if not args.no_parity:
                 v["rel_l2_vs_oracle"], _ = parity(vopts)
-            out["variants"][prec] = v
-            log(f"[bench] {prec}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
-                f"rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}")
+            out["variants"][name] = v
+            log(f"[bench] {name}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
+                f"backproject {vstage['backproject']:.3f} ms; rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}")
 
     if not args.no_bp:
         nz = max(1, min(args.bp_planes, a.n_scan))

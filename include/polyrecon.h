@@ -188,7 +188,8 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 1, 2, 4.  64 x kz_per_lane bins share one reference
  *                 wavenumber, so this also sets the range-grid step.
  *   waves         wavefronts per back-projection workgroup: 0 = automatic, or
- *                 4, 8 (8 only with the 8x8 tile).
+ *                 4, 8 (VALU kernel: 8 only with the 8x8 tile; MFMA kernel: 8
+ *                 only with the 16x8 and 16x16 tiles).
  *   mfma_backprojection  BF16 / FP16 modes only: 1 = back-project on the
  *                 matrix cores (PL_EUNSUPPORTED if the grid does not allow it);
  *                 0 (automatic) and -1 use the VALU back-projection.
@@ -198,7 +199,11 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 three split products per pair with FP32 accumulation.  It
  *                 needs the group's taps inside 16 samples; when the requested
  *                 oversampling makes them wider the plan lowers it (not below 4).
- * tile, kz_per_lane and waves are tuning knobs (FP32 back-projection); results
+ *                 Its tile is tile x tile_y pixels (16x16 by default; 8x8,
+ *                 16x8 and 16x16 allowed) and kz_block k_z bins (64 by
+ *                 default, or 128) share one workgroup and reference
+ *                 wavenumber.
+ * tile, tile_y, kz_per_lane, kz_block and waves are tuning knobs; results
  * agree to the method's tolerance whatever their values.
  */
 typedef struct pl_hybrid_opts {
@@ -210,6 +215,8 @@ typedef struct pl_hybrid_opts {
     int32_t kz_per_lane;
     int32_t waves;
     int32_t mfma_backprojection;
+    int32_t tile_y;
+    int32_t kz_block;
 } pl_hybrid_opts;
 
 /* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */

@@ -58,7 +58,8 @@ class ImageGridC(C.Structure):
 class HybridOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("interp", C.c_int32), ("l_oversample", C.c_double),
                 ("nufft_tol", C.c_double), ("tile", C.c_int32), ("kz_per_lane", C.c_int32),
-                ("waves", C.c_int32), ("mfma_backprojection", C.c_int32)]
+                ("waves", C.c_int32), ("mfma_backprojection", C.c_int32), ("tile_y", C.c_int32),
+                ("kz_block", C.c_int32)]
 
 
 class HybridPlanInfo(C.Structure):
@@ -202,13 +203,14 @@ def _grid(grid) -> ImageGridC:
 
 
 def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
-          waves=0, mfma_backprojection=0) -> HybridOpts:
+          waves=0, mfma_backprojection=0, tile_y=0, kz_block=0) -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {list(INTERPS)}")
     return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol),
-                      int(tile), int(kz_per_lane), int(waves), int(mfma_backprojection))
+                      int(tile), int(kz_per_lane), int(waves), int(mfma_backprojection), int(tile_y),
+                      int(kz_block))
 
 
 def check_sampling(geom: Geometry, grid) -> int:

@@ -77,7 +77,7 @@ struct HybridPlan {
     double x0 = 0, y0 = 0, dx = 0, dy = 0;
     int precision = PL_PREC_FP32, interp = PL_INTERP_BSPLINE4;
     double sigma_l = 8.0, tol = 1e-6;
-    int force_tile = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0;
+    int force_tile = 0, force_tile_y = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0, force_kb = 0;
     bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
     double half_band = 0, sigma_used = 0;
     // range grid and NUFFT
@@ -99,6 +99,7 @@ struct HybridPlan {
 };
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
+size_t backproject_mfma_lds_bytes(int n_ch, int kz_block);
 int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
               HybridPlan* p);
 

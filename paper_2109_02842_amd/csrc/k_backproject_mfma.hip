@@ -5,247 +5,332 @@
 // small dense product over a 16-sample window of the range grid:
 //   G[kz][p] += sum_s Q_c[kz][s] B_c[s][p],
 //   B_c[s][p] = K(x_p - s) exp(j k_ref l_c(p)),
-// with x_p the pixel's fractional position in the window and K the 4-tap
-// interpolation kernel written as a piecewise cubic (B-spline, Lagrange or
-// linear).  With the real embedding A = [Re Q | Im Q] (16 kz x 32):
+// with x_p the pixel's position in the window and K the 4-tap interpolation
+// kernel.  With the real embedding A = [Re Q | Im Q] (16 kz x 32):
 //   Re G = A [Re B; -Im B],   Im G = A [Im B; Re B],
-// two v_mfma_f32_16x16x32_bf16 per split product; operands are BF16 hi + lo
-// parts and each pair takes hi*hi + hi*lo + lo*hi (FP32 accumulation).
+// one v_mfma_f32_16x16x32_bf16 each per split product; operands are BF16
+// hi + lo parts and each pair takes hi*hi + hi*lo + lo*hi (FP32 accumulation).
 //
-// Block = 8x8 pixel tile (four 4x4 groups, one per wavefront) x a block of up
-// to 256 k_z bins sharing one reference wavenumber.  The range profiles
-// arrive already split (four BF16 planes per (channel, k_z)); each channel's
-// window rows are copied into LDS by direct global-to-LDS loads issued one
-// channel ahead (double buffer, one barrier per channel).  A wavefront
-// computes the weights of its 16 pixels for 4 channels at a time (one lane
-// per pair, float64 range and carrier phase), shares them with shuffles, and
-// builds its B operand in registers.
+// Workgroup = TX x TY pixel tile (4x4 groups, GPW per wavefront, NW wavefronts) x KB k_z
+// bins sharing one reference wavenumber.  The range profiles arrive split
+// (four BF16 planes per (channel, k_z): Re hi, Re lo, Im hi, Im lo).  For
+// each channel the tile's window rows are copied into LDS by 16-byte direct
+// global-to-LDS loads, one channel ahead (double buffer, one barrier per
+// channel).
+//
+// LDS row of one k_z bin: 33 chunks of 16 bytes; plane p occupies chunks
+// [8p, 8p + 8) (its first nck chunks hold the window, nck <= 8) and chunk 32
+// is padding.  A half-wave's A-operand read (16 rows x 2 lane groups x 8
+// bytes) then falls on distinct banks whether the LDS serves 32 or 64 lanes
+// per cycle: the row stride is an odd number of chunks and the imaginary
+// planes sit 256 bytes after the real ones.  All read offsets are constants.
+//
+// K-index order: lane group kg = lane / 16 of an operand holds samples
+// {4h .. 4h+3, 8+4h .. 8+4h+3} (h = kg & 1) of the real (kg < 2) or the
+// imaginary (kg >= 2) plane, so each A fragment is two aligned 8-byte reads.
+#include <cstring>
+
 #include "device.hpp"
 
 namespace pl {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kRowChunks = 33;              // 16-byte chunks per LDS row
+constexpr int kRowBytes = 16 * kRowChunks;  // 528
+constexpr int kPlaneBytes = 128;            // 8 chunks per plane
+constexpr int kSelEntries = 20;             // selector table: a0 = 4h - d0 in [-15, 4]
 
 struct BpmArgs {
-    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, wp, rsd, kb;
-    double x0, y0, dx, dy, du, inv_du, reach;
-    float kc[2][4];  // K(x): |x| < 1 -> poly(kc[1], |x|); 1 <= |x| < 2 -> poly(kc[0], |x| - 1)
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, win_bytes;
+    double x0, y0, dx, dy, inv_du, reach;
+    float coef[4][4];  // tap j weight = sum_k coef[j][k] t^k, taps at floor(u) - 1 + j
     double kref[kMaxBlocks];
 };
 
-__device__ __forceinline__ float kernel_eval(float x, const float (&kc)[2][4]) {
-    const float ax = fabsf(x);
-    const float z = ax - 1.f;
-    const float y1 = ((kc[1][3] * ax + kc[1][2]) * ax + kc[1][1]) * ax + kc[1][0];
-    const float y0 = ((kc[0][3] * z + kc[0][2]) * z + kc[0][1]) * z + kc[0][0];
-    return ax < 1.f ? y1 : (ax < 2.f ? y0 : 0.f);
+// Two floats to a packed BF16 pair (round to nearest even), one instruction.
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2{lo, hi}), bf16x2));
 }
 
-__device__ __forceinline__ unsigned bf16_bits(float x) {
-    return static_cast<unsigned>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(x)));
-}
-__device__ __forceinline__ float bf16_value(unsigned b) { return __uint_as_float(b << 16); }
-
-// Split 8 values into packed BF16 hi and lo fragments (x = hi + lo).
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
-    u32x4 h, l;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const unsigned a = bf16_bits(v[2 * k]), b = bf16_bits(v[2 * k + 1]);
-        h[k] = a | (b << 16);
-        const unsigned c = bf16_bits(v[2 * k] - bf16_value(a)), d = bf16_bits(v[2 * k + 1] - bf16_value(b));
-        l[k] = c | (d << 16);
-    }
-    hi = __builtin_bit_cast(bf16x8, h);
-    lo = __builtin_bit_cast(bf16x8, l);
+// Split x = hi + lo for the two values packed in h (BF16 pair of (x0, x1)).
+__device__ __forceinline__ unsigned pack_lo(float x0, float x1, unsigned h) {
+    return pack_bf16(x0 - __uint_as_float(h << 16), x1 - __uint_as_float(h & 0xffff0000u));
 }
 
-template <int KB>
-__global__ __launch_bounds__(256) void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
+// v_perm selector bytes of tap k (two bytes of a BF16 value) or zero bytes.
+__host__ __device__ constexpr unsigned tap_sel(int k) {
+    return (k >= 0 && k < 4) ? 0x0100u + 0x0202u * static_cast<unsigned>(k) : 0x0c0cu;
+}
+
+// sqrt(x) for x >= 0 to double precision: hardware FP32 root (about 1 ulp),
+// then one Newton step whose residual is formed in FP64.
+__device__ __forceinline__ double sqrt_dp(double x) {
+    const float r = __builtin_amdgcn_sqrtf(static_cast<float>(x));
+    const double rd = r;
+    const float corr = static_cast<float>(x - rd * rd) * (0.5f * __builtin_amdgcn_rcpf(r));
+    return r > 0.f ? rd + static_cast<double>(corr) : 0.0;
+}
+
+// 16-byte direct global-to-LDS copy.  The 16-byte form of the builtin exists
+// for the device target only; the host pass of this translation unit, which
+// emits the launch stubs, must not see it.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PL_DMA16(SRC, DST) __builtin_amdgcn_global_load_lds((SRC), (DST), 16, 0, 0)
+#else
+#define PL_DMA16(SRC, DST) ((void)(SRC), (void)(DST))
+#endif
+
+// This wavefront's share of one channel's window rows: instruction
+// i = wave + NW j fills LDS chunks [64 i, 64 i + 64) of the buffer at DST0;
+// lanes whose chunk is padding or beyond the window (doff = ~0) are idle.
+#define PL_STAGE_ROWS(BASE, DST0)                                                  \
+    do {                                                                           \
+        const char* base_ = (BASE);                                                \
+        unsigned char* dst0_ = (DST0);                                             \
+        _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                        \
+            const int i_ = wave + NW * j_;                                         \
+            if (i_ * 64 < KB * kRowChunks && doff[j_] != ~0u)                      \
+                PL_DMA16(base_ + doff[j_], dst0_ + i_ * 1024);                     \
+        }                                                                          \
+    } while (0)
+
+// Eight-wavefront workgroups aim at four wavefronts per SIMD (two
+// workgroups per CU), which caps a wavefront at 128 registers.
+template <int GPW, int KT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 1)))
+void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                                                                const double* __restrict__ chan,
                                                                const double* __restrict__ llo, BpmArgs a,
                                                                float2* __restrict__ G) {
-    constexpr int KT = KB / 16;  // k_z tiles of 16
-    extern __shared__ unsigned smem_u[];
-    int* win = reinterpret_cast<int*>(smem_u);                       // n_ch window starts (even)
-    unsigned* rows = smem_u + ((a.n_ch + 63) & ~63);                  // [2][KB][rsd] dwords
+    constexpr int KB = 16 * KT;
+    constexpr int NG = GPW * NW;                                    // groups per tile
+    constexpr int GX = NG == 4 ? 2 : 4, GY = NG / GX;
+    static_assert(NG == 4 || NG == 8 || NG == 16, "8x8, 16x8 or 16x16 pixel tiles");
+    constexpr int TX = 4 * GX, TY = 4 * GY;
+    constexpr int NIW = (KB * kRowChunks + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
+    constexpr unsigned kBufBytes = KB * kRowBytes;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    int* win = reinterpret_cast<int*>(smem);
+    u32x4* sel_tab = reinterpret_cast<u32x4*>(smem + a.win_bytes);
+    const unsigned lds0 = static_cast<unsigned>(a.win_bytes + kSelEntries * 16);
 
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-    if (work >= a.n_work) return;  // block-uniform, before any barrier
+    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
     const int blk = work / a.n_tiles;
     const int tile = work - blk * a.n_tiles;
-    const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
+    const int tx0 = (tile % a.tiles_x) * TX, ty0 = (tile / a.tiles_x) * TY;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpl = 8 * a.nck;  // staged samples per plane
     const double kref_rev = a.kref[blk] * (0.5 / kPi);
-    const int buf_dw = KB * a.rsd;
 
     // even window start of every channel for this tile
     {
-        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
-        for (int c = tid; c < a.n_ch; c += 256) {
+        const double cx = a.x0 + (tx0 + 0.5 * (TX - 1)) * a.dx, cy = a.y0 + (ty0 + 0.5 * (TY - 1)) * a.dy;
+        for (int c = tid; c < a.n_ch; c += 64 * NW) {
             const double* ch = chan + 4 * c;
             const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
                              sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
             int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
-            s = max(0, min(s, a.n_l - a.wp));
+            s = max(0, min(s, a.n_l - wpl));
             win[c] = s & ~1;
         }
     }
-    __syncthreads();
-
-    // Direct global-to-LDS staging: row r of the buffer holds, for k_z bin
-    // blk*KB + r, the window's 4 BF16 planes (wp samples each) = 2 wp dwords.
-    // Lane t of a row copies dword t (t < 2 wp; a second pass covers t >= 64).
-    const int half = a.wp / 2;
-    const int t0 = lane, t1 = lane + 64;
-    const unsigned lane_off0 = (t0 < 2 * a.wp) ? ((t0 / half) * a.n_l + 2 * (t0 % half)) * 2u : 0u;
-    const unsigned lane_off1 = (t1 < 2 * a.wp) ? ((t1 / half) * a.n_l + 2 * (t1 % half)) * 2u : 0u;
-    const bool two_pass = 2 * a.wp > 64;
-    const int rows_per_wave = KB / 4;
-    auto stage = [&](int c, int buf) {
-        const int s0 = __builtin_amdgcn_readfirstlane(win[c]);
-        for (int r = wave * rows_per_wave; r < (wave + 1) * rows_per_wave; ++r) {
-            const int kz = min(blk * KB + r, a.n_z - 1);
-            const char* rowg = reinterpret_cast<const char*>(
-                qs + ((static_cast<size_t>(c) * a.n_z + kz) * 4) * a.n_l + s0);
-            unsigned* dst = rows + buf * buf_dw + r * a.rsd;
-            if (t0 < 2 * a.wp)
-                __builtin_amdgcn_global_load_lds(rowg + lane_off0, dst, 4, 0, 0);
-            if (two_pass && t1 < 2 * a.wp)
-                __builtin_amdgcn_global_load_lds(rowg + lane_off1, dst + 64, 4, 0, 0);
-        }
-    };
-
-    // this wavefront's 4x4 group and this lane's pixel in the weight batch
-    const int gx = tx0 + 4 * (wave & 1), gy = ty0 + 4 * (wave >> 1);
-    const int pn = lane & 15;                       // pixel of the group
-    const int px = gx + (pn & 3), py = gy + (pn >> 2);
-    const bool pvalid = px < a.nx && py < a.ny;
-    const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
-    const int kg = lane >> 4;                       // k' group of the MFMA operands
-
-    f32x4 accr[KT], acci[KT];
+    // selectors of the sample pairs (a, a+1), (a+2, a+3), (a+8, a+9),
+    // (a+10, a+11) in tap units, a = a0 = 4h - d0, entry a0 + 15
+    if (tid < kSelEntries) {
+        const int a0 = tid - 15;
+        u32x4 e;
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-        accr[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int o = 0; o < 4; ++o) {
+            const int k = a0 + 2 * (o & 1) + 8 * (o >> 1);
+            e[o] = tap_sel(k) | (tap_sel(k + 1) << 16);
+        }
+        sel_tab[tid] = e;
     }
 
-    stage(0, 0);
+    // Per-lane byte offsets of this wavefront's DMA chunks (relative to the
+    // channel's window start), ~0 for idle lanes.
+    unsigned doff[NIW];
+#pragma unroll
+    for (int j = 0; j < NIW; ++j) {
+        const int g = (wave + NW * j) * 64 + lane;
+        const int r = g / kRowChunks, jj = g - r * kRowChunks;
+        const int part = jj >> 3, k8 = jj & 7;
+        const int kz = min(blk * KB + r, a.n_z - 1);
+        doff[j] = (r < KB && jj < 32 && k8 < a.nck) ? static_cast<unsigned>(((kz * 4 + part) * a.n_l + 8 * k8) * 2)
+                                                   : ~0u;
+    }
+    const size_t chan_elems = static_cast<size_t>(a.n_z) * 4 * a.n_l;
+
+    // pixel of this lane within a group, k' group of the MFMA operands
+    const int pn = lane & 15, kg = lane >> 4, h = kg & 1;
+    int gpx[GPW], gpy[GPW];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g) {
+        const int gi = wave * GPW + g;
+        gpx[g] = tx0 + 4 * (gi % GX) + (pn & 3);
+        gpy[g] = ty0 + 4 * (gi / GX) + (pn >> 2);
+    }
+
+    f32x4 accr[GPW][KT], acci[GPW][KT];
+#pragma unroll
+    for (int g = 0; g < GPW; ++g)
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            accr[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acci[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+
+    __syncthreads();  // window starts and selector table visible
+    PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + __builtin_amdgcn_readfirstlane(win[0])), smem + lds0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // LDS dword offset of this lane's A operand: row m = lane & 15 of the
-    // k_z tile, plane (Re or Im) hi, samples 8 * (kg & 1) + 0..7 of the window
-    const int a_row = (lane & 15) * a.rsd;
-    const int a_plane = (kg < 2 ? 0 : 2) * half + 4 * (kg & 1);
+    // LDS byte offset of this lane's A operand within a buffer: row m = lane
+    // & 15 of a k_z tile, hi plane (0 real, 2 imaginary), samples 4h.. of the
+    // group window; the lo plane is kPlaneBytes further
+    const unsigned a_lane = static_cast<unsigned>(pn * kRowBytes) + (kg < 2 ? 0u : 2u * kPlaneBytes) + 8u * h;
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
-        // weights of (pixel pn, channel c0 + lane / 16)
-        float x_rel = 100.f, cr = 0.f, ci = 0.f;
-        int srel = 0;
+        // weights of (pixel pn of group g, channel c0 + lane / 16)
+        float xw[GPW], crw[GPW], ciw[GPW];
+        int srw[GPW];
         {
-            const int c = c0 + (lane >> 4);
-            int i0 = 0x3fffffff;
-            double u = 0.0;
-            double lpath = 0.0;
-            const bool ok = c < a.n_ch && pvalid;
-            if (ok) {
-                const double* ch = chan + 4 * c;
-                lpath = sqrt((xg - ch[0]) * (xg - ch[0]) + (yg - ch[1]) * (yg - ch[1])) +
-                        sqrt((xg - ch[2]) * (xg - ch[2]) + (yg - ch[3]) * (yg - ch[3]));
-                u = (lpath - llo[c]) * a.inv_du;
-                i0 = static_cast<int>(floor(u)) - 1;
-            }
-            // first tap of the group (16 lanes of the same channel)
-            int m = i0;
-            m = min(m, __shfl_xor(m, 1));
-            m = min(m, __shfl_xor(m, 2));
-            m = min(m, __shfl_xor(m, 4));
-            m = min(m, __shfl_xor(m, 8));
-            const int cw = win[min(c, a.n_ch - 1)];
-            srel = m == 0x3fffffff ? 0 : max(0, min(m - cw, a.wp - 16)) & ~1;
-            if (ok) {
-                x_rel = static_cast<float>(u - static_cast<double>(cw + srel));
-                const float2 car = cis_rev(kref_rev * lpath);
-                cr = car.x;
-                ci = car.y;
+            const int c = min(c0 + (lane >> 4), a.n_ch - 1);
+            const double* ch = chan + 4 * c;
+            const double xT = ch[0], yT = ch[1], xR = ch[2], yR = ch[3], lo = llo[c];
+            const int cw = win[c];
+#pragma unroll
+            for (int g = 0; g < GPW; ++g) {
+                const bool ok = gpx[g] < a.nx && gpy[g] < a.ny;
+                const double xg = a.x0 + gpx[g] * a.dx, yg = a.y0 + gpy[g] * a.dy;
+                const double lpath = sqrt_dp((xg - xT) * (xg - xT) + (yg - yT) * (yg - yT)) +
+                                     sqrt_dp((xg - xR) * (xg - xR) + (yg - yR) * (yg - yR));
+                const double u = (lpath - lo) * a.inv_du;
+                int m = ok ? static_cast<int>(floor(u)) - 1 : 0x3fffffff;
+                m = min(m, __shfl_xor(m, 1));
+                m = min(m, __shfl_xor(m, 2));
+                m = min(m, __shfl_xor(m, 4));
+                m = min(m, __shfl_xor(m, 8));
+                const int sr = m == 0x3fffffff ? 0 : max(0, min((m - cw) & ~3, wpl - 16));
+                srw[g] = sr;
+                xw[g] = ok ? static_cast<float>(u - static_cast<double>(cw + sr)) : 1000.f;
+                const float2 car = ok ? cis_rev(kref_rev * lpath) : make_float2(0.f, 0.f);
+                crw[g] = car.x;
+                ciw[g] = car.y;
             }
         }
 #pragma unroll 1
         for (int cc = 0; cc < 4; ++cc) {
             const int c = c0 + cc;
             if (c >= a.n_ch) break;
-            if (c + 1 < a.n_ch) stage(c + 1, (c + 1) & 1);
-            // B operand of this channel: lane (pixel n = lane & 15, k' group kg)
-            const int src = cc * 16 + (lane & 15);
-            const float xn = __shfl(x_rel, src), crn = __shfl(cr, src), cin = __shfl(ci, src);
-            const int sr = __builtin_amdgcn_readlane(srel, cc * 16);
-            const float ca = kg < 2 ? crn : -cin;   // rows of Re Q: Re B (for Re G), Im B (for Im G)
-            const float cb = kg < 2 ? cin : crn;    // rows of Im Q: -Im B, Re B
-            float vr[8], vi[8];
+            if (c + 1 < a.n_ch)
+                PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + (c + 1) * chan_elems +
+                                                            __builtin_amdgcn_readfirstlane(win[c + 1])),
+                              smem + lds0 + ((c + 1) & 1) * kBufBytes);
+            const unsigned bufo = lds0 + (c & 1) * kBufBytes;
+            const int src = cc * 16 + pn;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float kv = kernel_eval(xn - static_cast<float>(8 * (kg & 1) + t), a.kc);
-                vr[t] = kv * ca;
-                vi[t] = kv * cb;
-            }
-            bf16x8 brh, brl, bih, bil;
-            split8(vr, brh, brl);
-            split8(vi, bih, bil);
-            // A operand rows from LDS, one k_z tile at a time
-            const unsigned* abase = rows + (c & 1) * buf_dw + a_row + a_plane + sr / 2;
+            for (int g = 0; g < GPW; ++g) {
+                // B operand: taps of this lane's pixel times the carrier,
+                // placed at its 8 samples by byte permutes
+                const float xn = __shfl(xw[g], src), crn = __shfl(crw[g], src), cin = __shfl(ciw[g], src);
+                const int sr = __builtin_amdgcn_readlane(srw[g], cc * 16);
+                const float fl = floorf(xn);
+                const float t = xn - fl;
+                // a0 = 4h - d0 with d0 = floor(x) - 1 the first tap in the group window
+                const int a0 = min(max(4 * h + 1 - static_cast<int>(fl), -15), 4);
+                const u32x4 sel = sel_tab[a0 + 15];
+                float w[4];
 #pragma unroll
-            for (int t = 0; t < KT; ++t) {
-                const unsigned* ap = abase + t * 16 * a.rsd;
-                const u32x4 ah = u32x4{ap[0], ap[1], ap[2], ap[3]};
-                const u32x4 al = u32x4{ap[half + 0], ap[half + 1], ap[half + 2], ap[half + 3]};
-                const bf16x8 vah = __builtin_bit_cast(bf16x8, ah), val = __builtin_bit_cast(bf16x8, al);
-                accr[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brh, accr[t], 0, 0, 0);
-                acci[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bih, acci[t], 0, 0, 0);
-                accr[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brl, accr[t], 0, 0, 0);
-                acci[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bil, acci[t], 0, 0, 0);
-                accr[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, brh, accr[t], 0, 0, 0);
-                acci[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, bih, acci[t], 0, 0, 0);
+                for (int j = 0; j < 4; ++j)
+                    w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
+                const float ca = kg < 2 ? crn : -cin;  // rows of Re Q: Re B (Re G), Im B (Im G)
+                const float cb = kg < 2 ? cin : crn;   // rows of Im Q: -Im B, Re B
+                const float r0 = w[0] * ca, r1 = w[1] * ca, r2 = w[2] * ca, r3 = w[3] * ca;
+                const float i0 = w[0] * cb, i1 = w[1] * cb, i2 = w[2] * cb, i3 = w[3] * cb;
+                const unsigned rh0 = pack_bf16(r0, r1), rh1 = pack_bf16(r2, r3);
+                const unsigned ih0 = pack_bf16(i0, i1), ih1 = pack_bf16(i2, i3);
+                const unsigned rl0 = pack_lo(r0, r1, rh0), rl1 = pack_lo(r2, r3, rh1);
+                const unsigned il0 = pack_lo(i0, i1, ih0), il1 = pack_lo(i2, i3, ih1);
+                u32x4 vrh, vrl, vih, vil;
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    vrh[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
+                    vrl[o] = __builtin_amdgcn_perm(rl1, rl0, sel[o]);
+                    vih[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
+                    vil[o] = __builtin_amdgcn_perm(il1, il0, sel[o]);
+                }
+                const bf16x8 brh = __builtin_bit_cast(bf16x8, vrh), brl = __builtin_bit_cast(bf16x8, vrl);
+                const bf16x8 bih = __builtin_bit_cast(bf16x8, vih), bil = __builtin_bit_cast(bf16x8, vil);
+                const unsigned char* ap = smem + bufo + a_lane + 2u * static_cast<unsigned>(sr);
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    const unsigned char* p = ap + t * 16 * kRowBytes;
+                    const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
+                    const u32x2 h1 = *reinterpret_cast<const u32x2*>(p + 16);
+                    const u32x2 l0 = *reinterpret_cast<const u32x2*>(p + kPlaneBytes);
+                    const u32x2 l1 = *reinterpret_cast<const u32x2*>(p + kPlaneBytes + 16);
+                    const bf16x8 vah = __builtin_bit_cast(bf16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
+                    const bf16x8 val = __builtin_bit_cast(bf16x8, u32x4{l0[0], l0[1], l1[0], l1[1]});
+                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brh, accr[g][t], 0, 0, 0);
+                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bih, acci[g][t], 0, 0, 0);
+                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brl, accr[g][t], 0, 0, 0);
+                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bil, acci[g][t], 0, 0, 0);
+                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, brh, accr[g][t], 0, 0, 0);
+                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, bih, acci[g][t], 0, 0, 0);
+                }
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
     }
 
-    // D layout: lane holds column (pixel) lane & 15, rows 4 * (lane >> 4) + v
-    if (pvalid) {
-        float2* out = G + (static_cast<size_t>(py) * a.nx + px) * a.n_z;
+    // D layout: lane holds column (pixel) lane & 15, rows 4 (lane / 16) + v
 #pragma unroll
-        for (int t = 0; t < KT; ++t) {
+    for (int g = 0; g < GPW; ++g) {
+        if (gpx[g] < a.nx && gpy[g] < a.ny) {
+            float2* out = G + (static_cast<size_t>(gpy[g]) * a.nx + gpx[g]) * a.n_z;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int kz = blk * KB + 16 * t + 4 * kg + v;
-                if (kz < a.n_z) out[kz] = make_float2(accr[t][v], acci[t][v]);
+            for (int t = 0; t < KT; ++t) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kz = blk * KB + 16 * t + 4 * kg + v;
+                    if (kz < a.n_z) out[kz] = make_float2(accr[g][t][v], acci[g][t][v]);
+                }
             }
         }
     }
 }
 
-template <int KB>
-int launch_kb(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, const unsigned short* qs,
-              const double* chan, const double* llo, float2* G) {
-    auto fn = backproject_mfma_kernel<KB>;
+template <int GPW, int KT, int NW>
+int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, const unsigned short* qs,
+               const double* chan, const double* llo, float2* G) {
+    auto fn = backproject_mfma_kernel<GPW, KT, NW>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
-        if (e != hipSuccess) return fail(PL_EDEVICE, "MFMA back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
+        if (e != hipSuccess)
+            return fail(PL_EDEVICE, "MFMA back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), smem, s, qs, chan, llo, a, G);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, qs, chan, llo, a, G);
     return check_launch("back-projection (MFMA)");
 }
 
 }  // namespace
+
+size_t backproject_mfma_lds_bytes(int n_ch, int kz_block) {
+    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + kSelEntries * 16 + 2ull * kz_block * kRowBytes;
+}
 
 int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs, char* ws,
                             float2* G, hipStream_t s) {
@@ -259,34 +344,35 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
     a.n_tiles = p.tiles_x * p.tiles_y;
     a.n_work = a.n_tiles * p.n_blocks;
     a.per_xcd = (a.n_work + 7) / 8;
-    a.wp = p.window;
-    a.rsd = p.window_pad;
-    a.kb = p.block;
+    a.nck = p.window / 8;
+    a.win_bytes = ((p.n_ch + 3) & ~3) * 4;
     a.x0 = p.x0;
     a.y0 = p.y0;
     a.dx = p.dx;
     a.dy = p.dy;
-    a.du = p.du;
     a.inv_du = 1.0 / p.du;
-    a.reach = std::hypot(7.0 * p.dx, 7.0 * p.dy);
-    for (int j = 0; j < 4; ++j) {
-        a.kc[0][j] = p.coef[0][j];
-        a.kc[1][j] = p.coef[1][j];
-    }
+    a.reach = std::hypot((p.tile_x - 1) * p.dx, (p.tile_y - 1) * p.dy);  // 2 x tile half-diagonal
+    std::memcpy(a.coef, p.coef, sizeof(a.coef));
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
-    if (p.window < 16 || p.window > 64 || (p.window & 1) || p.window > p.n_l || p.window_pad != 2 * p.window + 1)
+    if (p.window % 8 || a.nck < 2 || a.nck > 8 || p.window > p.n_l || p.window_pad != kRowChunks)
         return fail(PL_EUNSUPPORTED, "MFMA back-projection window %d out of range", p.window);
-    const size_t smem = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * p.block * p.window_pad * 4;
+    const size_t smem = backproject_mfma_lds_bytes(p.n_ch, p.block);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "MFMA back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
-    switch (p.block) {
-        case 64: return launch_kb<64>(a, smem, blocks, s, qs, dt.chan, llo, G);
-        case 128: return launch_kb<128>(a, smem, blocks, s, qs, dt.chan, llo, G);
-        case 192: return launch_kb<192>(a, smem, blocks, s, qs, dt.chan, llo, G);
-        case 256: return launch_kb<256>(a, smem, blocks, s, qs, dt.chan, llo, G);
-        default: return fail(PL_EUNSUPPORTED, "MFMA back-projection block of %d k_z bins", p.block);
-    }
+    const int ng = p.tile_x * p.tile_y / 16;
+    const int kt = p.block / 16;
+    const int nw = p.waves;
+#define PL_BPM(G_, K_, W_) \
+    if (ng == G_ * W_ && kt == K_ && nw == W_) return launch_cfg<G_, K_, W_>(a, smem, blocks, s, qs, dt.chan, llo, G);
+    PL_BPM(1, 4, 4) PL_BPM(1, 8, 4) PL_BPM(2, 4, 4) PL_BPM(2, 8, 4) PL_BPM(4, 4, 4) PL_BPM(4, 8, 4)
+    PL_BPM(1, 4, 8) PL_BPM(1, 8, 8) PL_BPM(2, 4, 8)
+#undef PL_BPM
+    return fail(PL_EUNSUPPORTED, "MFMA back-projection tile %dx%d with %d k_z bins and %d wavefronts", p.tile_x,
+                p.tile_y, p.block, p.waves);
 }
+
+#undef PL_STAGE_ROWS
+#undef PL_DMA16
 
 }  // namespace pl

@@ -71,13 +71,19 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.force_kpl = opts->kz_per_lane;
         p.force_waves = opts->waves;
         p.force_bp_mfma = opts->mfma_backprojection;
+        p.force_tile_y = opts->tile_y;
+        p.force_kb = opts->kz_block;
     }
     if (p.force_kpl != 0 && p.force_kpl != 1 && p.force_kpl != 2 && p.force_kpl != 4)
         return fail(PL_EINVAL, "kz_per_lane must be 0, 1, 2 or 4");
     if (p.force_waves != 0 && p.force_waves != 4 && p.force_waves != 8)
         return fail(PL_EINVAL, "waves must be 0, 4 or 8");
-    if (p.force_tile != 0 && p.force_tile != 8 && p.force_tile != 4 && p.force_tile != 2)
-        return fail(PL_EINVAL, "tile must be 0, 8, 4 or 2");
+    if (p.force_tile != 0 && p.force_tile != 16 && p.force_tile != 8 && p.force_tile != 4 && p.force_tile != 2)
+        return fail(PL_EINVAL, "tile must be 0, 16, 8, 4 or 2");
+    if (p.force_tile_y != 0 && p.force_tile_y != 16 && p.force_tile_y != 8)
+        return fail(PL_EINVAL, "tile_y must be 0, 16 or 8");
+    if (p.force_kb != 0 && p.force_kb != 64 && p.force_kb != 128)
+        return fail(PL_EINVAL, "kz_block must be 0, 64 or 128");
     if (p.precision < PL_PREC_FP32 || p.precision > PL_PREC_FP16)
         return fail(PL_EINVAL, "unknown precision %d", p.precision);
     if (p.interp < PL_INTERP_BSPLINE4 || p.interp > PL_INTERP_LINEAR)
@@ -124,36 +130,50 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.du = kPi / (sigma * half_band);
     };
 
-    // MFMA back-projection (BF16 / FP16 modes): 8x8 tiles of four 4x4 pixel
-    // groups, each group's taps inside one 16-sample window.  |l(p) - l(q)| <=
-    // 2 |p - q|, so a group spans at most 2 * diagonal / du samples plus the
-    // 4 taps and one sample each for flooring and even alignment.
+    // MFMA back-projection (BF16 / FP16 modes): tiles of 4x4 pixel groups,
+    // each group's taps inside one 16-sample window that starts on a multiple
+    // of 4 samples.  |l(p) - l(q)| <= 2 |p - q|, so a group's first tap is at
+    // most 3 samples past its window start and its last at most
+    // ceil(2 * diagonal / du) + 3 past its first.
     p.bp_mfma = false;
-    if (p.precision != PL_PREC_FP32 && p.force_bp_mfma > 0 && p.force_kpl == 0 && p.force_tile == 0 &&
-        p.force_waves == 0) {
-        const int kb = std::min(256, (p.n_z + 63) / 64 * 64);
+    if (p.force_bp_mfma > 0) {
+        if (p.precision == PL_PREC_FP32)
+            return fail(PL_EUNSUPPORTED, "the MFMA back-projection runs in the BF16 / FP16 modes only");
+        if (p.force_kpl != 0)
+            return fail(PL_EINVAL, "kz_per_lane applies to the VALU back-projection");
+        const int tx = p.force_tile ? p.force_tile : 16;
+        const int ty = p.force_tile_y ? p.force_tile_y : tx;
+        if (!((tx == 8 && ty == 8) || (tx == 16 && (ty == 8 || ty == 16))))
+            return fail(PL_EINVAL, "MFMA back-projection tiles are 8x8, 16x8 or 16x16");
+        const int kb = p.force_kb ? p.force_kb : 64;
         const double gdiag = std::hypot(3.0 * grid->dx, 3.0 * grid->dy);
         set_blocks(kb, p.sigma_l);
-        if (std::ceil(2.0 * gdiag / p.du) + 6 > 16) {
+        if (std::ceil(2.0 * gdiag / p.du) > 9) {
             // widest grid step that fits, as long as the oversampling stays >= 4
-            const double du_fit = 2.0 * gdiag / 9.999;
+            const double du_fit = 2.0 * gdiag / 8.999;
             const double sigma_fit = kPi / (du_fit * p.half_band);
             if (sigma_fit >= 4.0) set_blocks(kb, std::min(p.sigma_l, sigma_fit));
         }
-        const double rt = 0.5 * std::hypot(7.0 * grid->dx, 7.0 * grid->dy);
-        int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7;
-        wl = std::max(16, wl + (wl & 1));
-        const size_t lds = static_cast<size_t>((p.n_ch + 63) & ~63) * 4 + 2ull * kb * (2 * wl + 1) * 4;
-        if (std::ceil(2.0 * gdiag / p.du) + 6 <= 16 && wl <= 64 && lds <= kMaxLds && p.n_f <= 128) {
+        // staged window: every tap of the tile plus alignment (8-sample chunks)
+        const double rt = 0.5 * std::hypot((tx - 1) * grid->dx, (ty - 1) * grid->dy);
+        const int need = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
+        const int nck = std::max(2, (need + 7) / 8);
+        const size_t lds = backproject_mfma_lds_bytes(p.n_ch, kb);
+        if (std::ceil(2.0 * gdiag / p.du) <= 9 && nck <= 8 && lds <= kMaxLds && p.n_f <= 128) {
             p.bp_mfma = true;
-            p.tile_x = p.tile_y = 8;
-            p.window = wl;
-            p.window_pad = 2 * wl + 1;  // LDS row stride in dwords: 4 parts x wl bf16 + 1
-            p.waves = 4;
+            p.tile_x = tx;
+            p.tile_y = ty;
+            p.window = 8 * nck;  // samples staged per plane and row
+            p.window_pad = 33;   // LDS row length in 16-byte chunks (4 planes x 8 + 1)
+            p.waves = p.force_waves ? p.force_waves : 4;
+            if (tx * ty == 64 && p.waves == 8)
+                return fail(PL_EUNSUPPORTED, "8 wavefronts need a 16x8 or 16x16 MFMA tile");
+            if (tx * ty == 256 && kb == 128 && p.waves == 8)
+                return fail(PL_EUNSUPPORTED, "8 wavefronts with a 16x16 tile take 64 k_z bins");
         }
     }
     if (p.force_bp_mfma > 0 && !p.bp_mfma)
-        return fail(PL_EUNSUPPORTED, "the MFMA back-projection does not fit this grid (BF16/FP16 only)");
+        return fail(PL_EUNSUPPORTED, "the MFMA back-projection does not fit this grid");
     if (!p.bp_mfma) {
         // One k_z bin per lane by default: measured fastest on gfx950, since
         // more bins per lane make the staged window too large for several
@@ -180,6 +200,8 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // Back-projection tile: the staged range window must hold every tap of
     // the tile's pixels.  |l(p) - l(centre)| <= 2 * half-diagonal.
     if (!p.bp_mfma) {
+    if (p.force_tile == 16 || p.force_tile_y != 0 || p.force_kb != 0)
+        return fail(PL_EINVAL, "tile 16, tile_y and kz_block apply to the MFMA back-projection");
     // Prefer the largest tile whose window fits 64 samples (one staging load
     // per lane and row; the 2x2 fallback allows 128) and whose LDS (window
     // starts + two staged windows of 64 x kz_per_lane rows) fits the

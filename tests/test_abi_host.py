@@ -165,9 +165,22 @@ def test_mfma_backprojection_plan_rules():
     g = pr.make_geometry(W.C1.array)
     fine = _fine_grid(40, 40, 0.0015)
     p = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1)
-    assert p.mfma_backprojection and p.tile == (8, 8) and p.block % 64 == 0 and p.window % 2 == 0
-    # every 4x4 group's taps fit 16 samples: 2 x group diagonal / du + 6 <= 16
-    assert math.ceil(2 * math.hypot(3 * fine.dx, 3 * fine.dy) / p.du) + 6 <= 16
+    assert p.mfma_backprojection and p.tile == (16, 16) and p.block == 64 and p.window % 8 == 0
+    # every 4x4 group's taps fit a 16-sample window that starts on a multiple
+    # of 4: up to 3 samples of alignment, 2 x group diagonal / du, 4 taps
+    assert 3 + math.ceil(2 * math.hypot(3 * fine.dx, 3 * fine.dy) / p.du) + 3 <= 15
+    for tile, tile_y, kb in [(8, 8, 64), (16, 8, 128), (16, 16, 128)]:
+        q = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1, tile=tile, tile_y=tile_y,
+                                kz_block=kb)
+        assert q.tile == (tile, tile_y) and q.block == kb
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1, tile=8, tile_y=16)
+    assert e.value.code == pr.PL_EINVAL
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="bf16", tile=16)          # 16 is a matrix-core tile
+    assert e.value.code == pr.PL_EINVAL
+    with pytest.raises(pr.PolyreconError):
+        pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1, kz_block=96)
     assert not pr.hybrid_plan_info(g, fine, precision="fp32").mfma_backprojection
     q = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=-1)
     assert not q.mfma_backprojection and q.block == 64

@@ -213,8 +213,9 @@ def test_mfma_backprojection_matches_oracle(case, interp, precision):
             "C1": _fine_grid(44, 37, 0.0015)}[case]
     sigma = 16.0 if interp == "lagrange4" else 8.0
     g = pr.make_geometry(wl.array)
-    plan = pr.hybrid_plan_info(g, grid, precision=precision, interp=interp, l_oversample=sigma)
-    assert plan.mfma_backprojection and plan.tile == (8, 8) and plan.block % 64 == 0
+    plan = pr.hybrid_plan_info(g, grid, precision=precision, interp=interp, l_oversample=sigma,
+                               mfma_backprojection=1)
+    assert plan.mfma_backprojection and plan.tile == (16, 16) and plan.block == 64
     arr = ogeom.build(wl.array)
     s = W.random_echo(wl.array, 41)
     say("mfma backprojection", case, interp, precision, "window", plan.window, "block", plan.block)
@@ -229,6 +230,29 @@ def test_mfma_backprojection_matches_oracle(case, interp, precision):
     # linear taps carry their own interpolation error; the matrix cores must
     # not add to it beyond the split-BF16 rounding
     assert err < (1e-3 if interp != "linear" else 1.2 * err_valu + 1e-3)
+
+
+@pytest.mark.parametrize("tile,tile_y,kb,waves", [(8, 8, 64, 4), (8, 8, 128, 4), (16, 8, 64, 4), (16, 8, 128, 4),
+                                                   (16, 16, 64, 4), (16, 16, 128, 4), (16, 8, 64, 8),
+                                                   (16, 8, 128, 8), (16, 16, 64, 8)])
+def test_mfma_backprojection_tilings(tile, tile_y, kb, waves):
+    # every tiling of the workgroup gives the same image to the split-BF16 bar;
+    # 300 k_z bins leave a ragged last k_z block, 61 x 45 pixels ragged tiles
+    arr_desc = replace(W.C1.array, n_scan=300)
+    grid = _fine_grid(61, 45, 0.0015)
+    g = pr.make_geometry(arr_desc)
+    arr = ogeom.build(arr_desc)
+    s = W.random_echo(arr_desc, 43)
+    say("mfma tiling", tile, tile_y, kb, waves)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), precision="bf16", mfma_backprojection=1, tile=tile,
+                                     tile_y=tile_y, kz_block=kb, waves=waves))
+    kap = sorted(set(W.random_subset(300, 6, 44).tolist() + [0, 63, 64, 127, 128, 299]))
+    pix = np.unique(np.concatenate([W.random_subset(grid.nx * grid.ny, 200, 45), [0, grid.nx * grid.ny - 1]]))
+    px, py = ohyb.pixel_grid(grid)
+    ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
+    err = rel(_spectrum_subset(img, kap, pix), ref)
+    say("   rel L2", err)
+    assert err < 1e-3
 
 
 @pytest.mark.parametrize("wlname", ["tiny-mono", "tiny-multi", "multi-small", "C1"])
@@ -300,17 +324,19 @@ def _spectrum_subset(img, kappas, pix):
     return G[np.ix_(kappas, pix)]
 
 
-@pytest.mark.parametrize("wl,precision", [(W.C2, "fp32"), (W.C3, "fp32"), (W.C2, "bf16"), (W.C2, "fp16"),
-                                         (W.C3, "bf16")],
-                         ids=["C2-fp32", "C3-fp32", "C2-bf16", "C2-fp16", "C3-bf16"])
-def test_hybrid_full_size_sampled(wl, precision):
+@pytest.mark.parametrize("wl,precision,mfma_bp", [(W.C2, "fp32", 0), (W.C3, "fp32", 0), (W.C2, "bf16", 0),
+                                                 (W.C2, "fp16", 0), (W.C3, "bf16", 0), (W.C2, "bf16", 1),
+                                                 (W.C2, "fp16", 1), (W.C3, "bf16", 1)],
+                         ids=["C2-fp32", "C3-fp32", "C2-bf16", "C2-fp16", "C3-bf16", "C2-bf16-mfma-bp",
+                              "C2-fp16-mfma-bp", "C3-bf16-mfma-bp"])
+def test_hybrid_full_size_sampled(wl, precision, mfma_bp):
     # The full workload in the launch configuration the benchmark times;
     # the oracle evaluates sampled (k_z, pixel) pairs of the spectrum.
     g = pr.make_geometry(wl.array)
     arr = ogeom.build(wl.array)
     s = W.random_echo(wl.array, 21)
-    say("full size", wl.name, precision)
-    img = host(pr.reconstruct_hybrid(g, wl.grid, dev(s), precision=precision))
+    say("full size", wl.name, precision, "mfma back-projection" if mfma_bp else "")
+    img = host(pr.reconstruct_hybrid(g, wl.grid, dev(s), precision=precision, mfma_backprojection=mfma_bp))
     assert np.all(np.isfinite(img))
     npix = wl.grid.nx * wl.grid.ny
     kap = W.random_subset(wl.array.n_scan, 3, 31).tolist()
