@@ -174,6 +174,11 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
 #define PL_INTERP_LAGRANGE4 1 /* cubic Lagrange on the range samples             */
 #define PL_INTERP_LINEAR 2    /* linear (the simplest "1-D interpolation")       */
 
+/* Back-projection kernels (hybrid plan info). */
+#define PL_BP_KZ_LANES 0     /* VALU, one k_z bin per lane, weights broadcast */
+#define PL_BP_PIXEL_LANES 1  /* VALU, one pixel per lane, weights shared via LDS */
+#define PL_BP_MFMA 2         /* matrix cores, split-BF16 operands */
+
 /*
  * Options of the hybrid method.  Zero-initialised fields take the defaults.
  *   precision     PL_PREC_* (default FP32).
@@ -181,15 +186,22 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *   l_oversample  range-grid oversampling over the Nyquist rate of the
  *                 baseband range profile (default 8; >= 2).
  *   nufft_tol     NUFFT tolerance (default 1e-6; 1e-12 .. 1e-2).
+ * The FP32 back-projection (VALU) has two kernels.  By default one pixel of
+ * an 8x8 tile per lane (PL_BP_PIXEL_LANES); where the tile's range window
+ * exceeds 64 samples, or when kz_per_lane or 8 wavefronts are asked for, one
+ * k_z bin per lane on 8x8, 4x4 or 2x2 tiles (PL_BP_KZ_LANES).
  *   tile          back-projection pixel tile edge: 0 = automatic, or 8, 4, 2
- *                 (PL_EUNSUPPORTED if the forced tile's range window does not
- *                 fit).
- *   kz_per_lane   k_z bins per lane in the back-projection: 0 = automatic, or
+ *                 (16 for the MFMA kernel; PL_EUNSUPPORTED if the forced
+ *                 tile's range window does not fit).
+ *   kz_per_lane   k_z-per-lane kernel: k_z bins per lane, 0 = automatic, or
  *                 1, 2, 4.  64 x kz_per_lane bins share one reference
  *                 wavenumber, so this also sets the range-grid step.
+ *   kz_block      k_z bins per workgroup (one reference wavenumber): 0 =
+ *                 automatic (64); pixel-per-lane kernel 32 or 64, MFMA kernel
+ *                 64 or 128.
  *   waves         wavefronts per back-projection workgroup: 0 = automatic, or
- *                 4, 8 (VALU kernel: 8 only with the 8x8 tile; MFMA kernel: 8
- *                 only with the 16x8 and 16x16 tiles).
+ *                 4, 8 (VALU: 8 selects the k_z-per-lane kernel on the 8x8
+ *                 tile; MFMA: 8 only with the 16x8 and 16x16 tiles).
  *   mfma_backprojection  BF16 / FP16 modes only: 1 = back-project on the
  *                 matrix cores (PL_EUNSUPPORTED if the grid does not allow it);
  *                 0 (automatic) and -1 use the VALU back-projection.
@@ -200,9 +212,7 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 needs the group's taps inside 16 samples; when the requested
  *                 oversampling makes them wider the plan lowers it (not below 4).
  *                 Its tile is tile x tile_y pixels (16x16 by default; 8x8,
- *                 16x8 and 16x16 allowed) and kz_block k_z bins (64 by
- *                 default, or 128) share one workgroup and reference
- *                 wavenumber.
+ *                 16x8 and 16x16 allowed).
  * tile, tile_y, kz_per_lane, kz_block and waves are tuning knobs; results
  * agree to the method's tolerance whatever their values.
  */
@@ -230,7 +240,8 @@ typedef struct pl_hybrid_plan_info {
     int32_t window;      /* range samples staged per pixel tile and channel      */
     int32_t tile_x;      /* back-projection pixel tile                           */
     int32_t tile_y;
-    int32_t mfma_backprojection; /* 1 if the back-projection runs on the matrix cores */
+    int32_t bp_kernel;   /* back-projection kernel: PL_BP_KZ_LANES, PL_BP_PIXEL_LANES, PL_BP_MFMA */
+    int32_t waves;       /* wavefronts per back-projection workgroup             */
     double du;           /* range-grid step (m of rho_T + rho_R)                 */
     double beta;         /* exponential-of-semicircle kernel shape               */
     size_t workspace_bytes;

@@ -25,6 +25,7 @@ PL_OK, PL_EINVAL, PL_EGEOM, PL_EDEVICE, PL_EWORKSPACE, PL_EUNSUPPORTED = 0, -1, 
 PL_MONO, PL_MULTI = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 INTERPS = {"bspline4": 0, "lagrange4": 1, "linear": 2}
+BP_KERNELS = {0: "kz-lanes", 1: "pixel-lanes", 2: "mfma"}
 WARN_ELEMENT_SPACING, WARN_SCAN_STEP = 1, 2
 
 _ERRNAMES = {PL_EINVAL: "PL_EINVAL", PL_EGEOM: "PL_EGEOM", PL_EDEVICE: "PL_EDEVICE",
@@ -66,7 +67,7 @@ class HybridPlanInfo(C.Structure):
     _fields_ = [("n_kz", C.c_int32), ("n_l", C.c_int32), ("n_fine", C.c_int32),
                 ("kernel_width", C.c_int32), ("n_blocks", C.c_int32), ("block", C.c_int32),
                 ("window", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("mfma_backprojection", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
+                ("bp_kernel", C.c_int32), ("waves", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
                 ("workspace_bytes", C.c_size_t)]
 
 
@@ -233,7 +234,12 @@ class PlanInfo:
     beta: float
     workspace_bytes: int
     k_ref: list
-    mfma_backprojection: bool = False
+    bp_kernel: str = "kz-lanes"
+    waves: int = 4
+
+    @property
+    def mfma_backprojection(self) -> bool:
+        return self.bp_kernel == "mfma"
 
 
 def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
@@ -243,7 +249,8 @@ def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
                                   C.byref(info), C.cast(kref, _P)))
     return PlanInfo(info.n_kz, info.n_l, info.n_fine, info.kernel_width, info.n_blocks, info.block,
                     info.window, (info.tile_x, info.tile_y), info.du, info.beta,
-                    int(info.workspace_bytes), list(kref[: info.n_blocks]), bool(info.mfma_backprojection))
+                    int(info.workspace_bytes), list(kref[: info.n_blocks]), BP_KERNELS[info.bp_kernel],
+                    int(info.waves))
 
 
 def hybrid_workspace_bytes(geom: Geometry, grid, **opts) -> int:

@@ -79,6 +79,7 @@ struct HybridPlan {
     double sigma_l = 8.0, tol = 1e-6;
     int force_tile = 0, force_tile_y = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0, force_kb = 0;
     bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
+    bool bp_gather = false;          // VALU back-projection with one pixel per lane
     double half_band = 0, sigma_used = 0;
     // range grid and NUFFT
     int n_l = 0, n_fine = 0, W = 0;
@@ -100,6 +101,7 @@ struct HybridPlan {
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 size_t backproject_mfma_lds_bytes(int n_ch, int kz_block);
+size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks);
 int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
               HybridPlan* p);
 

@@ -235,7 +235,244 @@ int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s
     return check_launch("back-projection");
 }
 
+
+// ---------------------------------------------------------------------------
+// Pixel-per-lane variant (the default): one workgroup = one 8x8 pixel tile x
+// KB k_z bins; lane = pixel, wavefront w owns k_z rows [RW w, RW (w + 1)).
+// The weights and carrier of a (pixel, channel) pair are computed once per
+// workgroup (wavefront w for the w-th channel of a batch of 4, one batch
+// ahead) and shared through LDS, so nothing is broadcast per pixel.  Every
+// LDS read is a 16-byte aligned ds_read_b128 (8-byte aligned pairs run at
+// about half the rate on gfx950): a pixel reads the aligned samples
+// [2m, 2m + 5) around its four taps (two 16-byte reads and one 8-byte read,
+// m = first tap / 2) with five weights shifted by the parity of the first
+// tap (one of them zero), so a (pixel, k_z) term costs 40 bytes of LDS and
+// fourteen FMAs.  The channel's window rows (even start)
+// are copied into LDS by 16-byte direct global-to-LDS loads one channel
+// ahead, double-buffered.
+struct BpgArgs {
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nchk, win_bytes;
+    double x0, y0, dx, dy, inv_du, reach;
+    float coef[4][4];
+    double kref[kMaxBlocks];
+};
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PL_DMA16(SRC, DST) __builtin_amdgcn_global_load_lds((SRC), (DST), 16, 0, 0)
+#else
+#define PL_DMA16(SRC, DST) ((void)(SRC), (void)(DST))  // device-only builtin (host pass emits stubs)
+#endif
+
+constexpr int kGatherWaves = 4;   // wavefronts per workgroup
+constexpr int kGatherBatch = 4;   // channels per weight batch
+
+// RSC 16-byte chunks per LDS row, of which nchk are staged: the window's
+// chunks and one more, since a pixel may read one chunk past its last tap.
+template <int KB, int RSC>
+__global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(const float2* __restrict__ q,
+                                                                               const double* __restrict__ chan,
+                                                                               const double* __restrict__ llo,
+                                                                               BpgArgs a, float2* __restrict__ G) {
+    constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
+    constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
+    constexpr unsigned kBufBytes = KB * RSC * 16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    int* win = reinterpret_cast<int*>(smem);
+    float4* wts = reinterpret_cast<float4*>(smem + a.win_bytes);   // [2][NB][2][64]
+    const unsigned lds_q = static_cast<unsigned>(a.win_bytes + 2 * NB * 2 * 64 * 16);
+
+    const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
+    const int blk = work / a.n_tiles;
+    const int tile = work - blk * a.n_tiles;
+    const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpl = 2 * a.nchk;
+    const double kref_rev = a.kref[blk] * (0.5 / kPi);
+
+    // even window start of every channel for this tile
+    {
+        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
+        for (int c = tid; c < a.n_ch; c += 64 * NW) {
+            const double* ch = chan + 4 * c;
+            const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
+                             sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
+            int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
+            s = max(0, min(s, a.n_l - wpl));
+            win[c] = s & ~1;
+        }
+    }
+
+    // DMA chunk offsets (bytes from the channel's window start), ~0 = idle
+    unsigned doff[NIW];
+#pragma unroll
+    for (int j = 0; j < NIW; ++j) {
+        const int g = (wave + NW * j) * 64 + lane;
+        const int r = g / RSC, k = g - r * RSC;
+        const int kz = min(blk * KB + r, a.n_z - 1);
+        doff[j] = (r < KB && k < a.nchk) ? static_cast<unsigned>((kz * a.n_l + 2 * k) * 8) : ~0u;
+    }
+    const size_t chan_elems = static_cast<size_t>(a.n_z) * a.n_l;
+#define PL_STAGE_Q(C_, BUF_)                                                                          \
+    do {                                                                                              \
+        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems +                     \
+                                                          __builtin_amdgcn_readfirstlane(win[C_]));   \
+        unsigned char* dst_ = smem + lds_q + (BUF_) * kBufBytes;                                      \
+        _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                                          \
+            const int i_ = wave + NW * j_;                                                            \
+            if (i_ * 64 < KB * RSC && doff[j_] != ~0u) PL_DMA16(base_ + doff[j_], dst_ + i_ * 1024);  \
+        }                                                                                             \
+    } while (0)
+
+    // this lane's pixel
+    const int px = tx0 + (lane & 7), py = ty0 + (lane >> 3);
+    const bool pvalid = px < a.nx && py < a.ny;
+    const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
+
+    // weights of (this lane's pixel, channel c) into slot [par][wave]:
+    // five tap weights over the aligned samples (first tap's parity decides
+    // the shift), carrier, byte offset of the first chunk in the row
+    auto weights = [&](int c, int par) {
+        float w[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float cr = 0.f, ci = 0.f;
+        int off = 0;
+        if (c < a.n_ch && pvalid) {
+            const double* ch = chan + 4 * c;
+            const double l = sqrt((xg - ch[0]) * (xg - ch[0]) + (yg - ch[1]) * (yg - ch[1])) +
+                             sqrt((xg - ch[2]) * (xg - ch[2]) + (yg - ch[3]) * (yg - ch[3]));
+            const double u = (l - llo[c]) * a.inv_du;
+            const double fl = floor(u);
+            const float t = static_cast<float>(u - fl);
+            // the last chunk a pixel may read (past its taps) is staged too
+            const int i0 = max(0, min(static_cast<int>(fl) - 1 - win[c], wpl - 6));
+            const bool odd = i0 & 1;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
+            w[0] = odd ? 0.f : v[0];
+            w[1] = odd ? v[0] : v[1];
+            w[2] = odd ? v[1] : v[2];
+            w[3] = odd ? v[2] : v[3];
+            w[4] = odd ? v[3] : 0.f;
+            const float2 car = cis_rev(kref_rev * l);
+            cr = car.x;
+            ci = car.y;
+            off = (i0 & ~1) * 8;
+        }
+        float4* slot = wts + (par * NB + wave) * 2 * 64 + lane;
+        slot[0] = make_float4(w[0], w[1], w[2], w[3]);
+        slot[64] = make_float4(w[4], cr, ci, __int_as_float(off));
+    };
+
+    float2 acc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) acc[r] = make_float2(0.f, 0.f);
+
+    __syncthreads();  // window starts visible
+    weights(wave, 0);
+    PL_STAGE_Q(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const unsigned row0 = static_cast<unsigned>(wave * RW * RSC * 16);
+#pragma unroll 1
+    for (int c0 = 0, par = 0; c0 < a.n_ch; c0 += NB, par ^= 1) {
+#pragma unroll 1
+        for (int cc = 0; cc < NB; ++cc) {
+            const int c = c0 + cc;
+            if (c >= a.n_ch) break;
+            if (c + 1 < a.n_ch) PL_STAGE_Q(c + 1, (c + 1) & 1);
+            if (cc == 0 && c0 + NB < a.n_ch) weights(c0 + NB + wave, par ^ 1);
+            const float4* slot = wts + (par * NB + cc) * 2 * 64 + lane;
+            const float4 wa = slot[0], wb = slot[64];
+            const unsigned off = __float_as_uint(wb.w);
+            const unsigned char* rp = smem + lds_q + (c & 1) * kBufBytes + row0 + off;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const float4* cp = reinterpret_cast<const float4*>(rp + r * RSC * 16);
+                const float4 q01 = cp[0], q23 = cp[1];
+                const float2 q4 = *reinterpret_cast<const float2*>(cp + 2);
+                const float re = wa.x * q01.x + wa.y * q01.z + wa.z * q23.x + wa.w * q23.z + wb.x * q4.x;
+                const float im = wa.x * q01.y + wa.y * q01.w + wa.z * q23.y + wa.w * q23.w + wb.x * q4.y;
+                acc[r].x = fmaf(wb.y, re, acc[r].x);
+                acc[r].x = fmaf(-wb.z, im, acc[r].x);
+                acc[r].y = fmaf(wb.y, im, acc[r].y);
+                acc[r].y = fmaf(wb.z, re, acc[r].y);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    }
+#undef PL_STAGE_Q
+
+    if (pvalid) {
+        float2* out = G + (static_cast<size_t>(py) * a.nx + px) * a.n_z;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int kz = blk * KB + wave * RW + r;
+            if (kz < a.n_z) out[kz] = acc[r];
+        }
+    }
+}
+#undef PL_DMA16
+
+template <int KB, int RSC>
+int launch_gather(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
+                  const double* chan, const double* llo, float2* G) {
+    auto fn = backproject_gather_kernel<KB, RSC>;
+    if (smem > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+        if (e != hipSuccess) return fail(PL_EDEVICE, "back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kGatherWaves), smem, s, q, chan, llo, a, G);
+    return check_launch("back-projection (pixel per lane)");
+}
+
+int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws, float2* G, hipStream_t s) {
+    BpgArgs a{};
+    a.n_ch = p.n_ch;
+    a.n_z = p.n_z;
+    a.n_l = p.n_l;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.tiles_x = p.tiles_x;
+    a.n_tiles = p.tiles_x * p.tiles_y;
+    a.n_work = a.n_tiles * p.n_blocks;
+    a.per_xcd = (a.n_work + 7) / 8;
+    a.nchk = p.window / 2 + 1;  // staged chunks: the window and one more
+    a.win_bytes = ((p.n_ch + 3) & ~3) * 4;
+    a.x0 = p.x0;
+    a.y0 = p.y0;
+    a.dx = p.dx;
+    a.dy = p.dy;
+    a.inv_du = 1.0 / p.du;
+    a.reach = std::hypot(7.0 * p.dx, 7.0 * p.dy);  // 2 x half-diagonal of the 8x8 tile
+    for (int k = 0; k < 4; ++k)
+        for (int j = 0; j < 4; ++j) a.coef[k][j] = p.coef[k][j];
+    for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
+    if ((p.block != 32 && p.block != 64) || p.tile_x != 8 || p.tile_y != 8 || p.window % 2 || a.nchk < 3 ||
+        a.nchk > p.window_pad || 2 * a.nchk > p.n_l || p.waves != kGatherWaves)
+        return fail(PL_EUNSUPPORTED, "pixel-per-lane back-projection: window %d, block %d", p.window, p.block);
+    const size_t smem = backproject_gather_lds_bytes(p.n_ch, p.block, p.window_pad);
+    if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
+    const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
+    const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
+#define PL_G(KB, RSC) \
+    if (p.block == KB && p.window_pad == RSC) return launch_gather<KB, RSC>(a, smem, blocks, s, q, dt.chan, llo, G);
+    PL_G(64, 12) PL_G(64, 16) PL_G(64, 20) PL_G(64, 24) PL_G(64, 33)
+    PL_G(32, 12) PL_G(32, 16) PL_G(32, 20) PL_G(32, 24) PL_G(32, 33)
+#undef PL_G
+    return fail(PL_EUNSUPPORTED, "no pixel-per-lane back-projection for %d-chunk rows", p.window_pad);
+}
+
 }  // namespace
+
+size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks) {
+    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + 2ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
+}
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad) {
     return static_cast<size_t>((n_ch + 63) & ~63) * 4 + 2ull * rows * window_pad * 8;
@@ -243,6 +480,7 @@ size_t backproject_lds_bytes(int n_ch, int rows, int window_pad) {
 
 int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws, float2* G,
                        hipStream_t s) {
+    if (p.bp_gather) return run_gather(p, dt, q, ws, G, s);
     BpjArgs a{};
     a.n_ch = p.n_ch;
     a.n_z = p.n_z;

@@ -82,8 +82,8 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         return fail(PL_EINVAL, "tile must be 0, 16, 8, 4 or 2");
     if (p.force_tile_y != 0 && p.force_tile_y != 16 && p.force_tile_y != 8)
         return fail(PL_EINVAL, "tile_y must be 0, 16 or 8");
-    if (p.force_kb != 0 && p.force_kb != 64 && p.force_kb != 128)
-        return fail(PL_EINVAL, "kz_block must be 0, 64 or 128");
+    if (p.force_kb != 0 && p.force_kb != 32 && p.force_kb != 64 && p.force_kb != 128)
+        return fail(PL_EINVAL, "kz_block must be 0, 32, 64 or 128");
     if (p.precision < PL_PREC_FP32 || p.precision > PL_PREC_FP16)
         return fail(PL_EINVAL, "unknown precision %d", p.precision);
     if (p.interp < PL_INTERP_BSPLINE4 || p.interp > PL_INTERP_LINEAR)
@@ -146,6 +146,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         if (!((tx == 8 && ty == 8) || (tx == 16 && (ty == 8 || ty == 16))))
             return fail(PL_EINVAL, "MFMA back-projection tiles are 8x8, 16x8 or 16x16");
         const int kb = p.force_kb ? p.force_kb : 64;
+        if (kb == 32) return fail(PL_EINVAL, "the MFMA back-projection takes 64 or 128 k_z bins per workgroup");
         const double gdiag = std::hypot(3.0 * grid->dx, 3.0 * grid->dy);
         set_blocks(kb, p.sigma_l);
         if (std::ceil(2.0 * gdiag / p.du) > 9) {
@@ -174,12 +175,42 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     }
     if (p.force_bp_mfma > 0 && !p.bp_mfma)
         return fail(PL_EUNSUPPORTED, "the MFMA back-projection does not fit this grid");
+    // VALU back-projection: the pixel-per-lane kernel when its 8x8 tile's
+    // window fits (32 k_z bins per workgroup by default: the narrower k'
+    // band of a smaller block coarsens the range grid, and four workgroups
+    // fit a CU), else one k_z bin per lane (one bin per lane by default:
+    // more bins per lane make the staged window too large for several
+    // resident workgroups per CU).
+    p.bp_gather = false;
     if (!p.bp_mfma) {
-        // One k_z bin per lane by default: measured fastest on gfx950, since
-        // more bins per lane make the staged window too large for several
-        // resident workgroups per CU.
-        const int kpl = p.force_kpl ? p.force_kpl : 1;
-        set_blocks(kLanes * kpl, p.sigma_l);
+        if (p.force_tile == 16 || p.force_tile_y != 0)
+            return fail(PL_EINVAL, "tile 16 and tile_y apply to the MFMA back-projection");
+        if (p.force_kb && (p.force_kb > 64 || p.force_kpl))
+            return fail(PL_EINVAL, "the VALU back-projection takes kz_block 32 or 64 (pixel-per-lane kernel)");
+        if (p.force_kpl == 0 && (p.force_tile == 0 || p.force_tile == 8) &&
+            (p.force_waves == 0 || p.force_waves == 4)) {
+            // staged rows start on an even sample (16-byte copies) and hold
+            // the window plus one chunk (a pixel reads three aligned chunks
+            // around its four taps)
+            set_blocks(p.force_kb ? p.force_kb : 32, p.sigma_l);
+            const double rt = 0.5 * std::hypot(7.0 * grid->dx, 7.0 * grid->dy);
+            const int nchk = (static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7 + 1) / 2;  // 2-sample chunks
+            const int rows[5] = {12, 16, 20, 24, 33};
+            int rsc = 0;
+            for (int r : rows)
+                if (!rsc && nchk + 1 <= r) rsc = r;
+            if (rsc && backproject_gather_lds_bytes(p.n_ch, p.block, rsc) <= kMaxLds) {
+                p.bp_gather = true;
+                p.tile_x = p.tile_y = 8;
+                p.window = 2 * nchk;   // samples staged per row
+                p.window_pad = rsc;    // LDS row length in 16-byte chunks
+                p.waves = 4;
+            }
+        }
+        if (!p.bp_gather) {
+            if (p.force_kb) return fail(PL_EUNSUPPORTED, "kz_block needs the pixel-per-lane back-projection");
+            set_blocks(kLanes * (p.force_kpl ? p.force_kpl : 1), p.sigma_l);
+        }
     }
 
     // Range window of every channel over the pixel-centre rectangle.
@@ -197,38 +228,36 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         span = std::max(span, lmax - lmin);
     }
 
-    // Back-projection tile: the staged range window must hold every tap of
-    // the tile's pixels.  |l(p) - l(centre)| <= 2 * half-diagonal.
-    if (!p.bp_mfma) {
-    if (p.force_tile == 16 || p.force_tile_y != 0 || p.force_kb != 0)
-        return fail(PL_EINVAL, "tile 16, tile_y and kz_block apply to the MFMA back-projection");
-    // Prefer the largest tile whose window fits 64 samples (one staging load
-    // per lane and row; the 2x2 fallback allows 128) and whose LDS (window
-    // starts + two staged windows of 64 x kz_per_lane rows) fits the
-    // workgroup's 160 KiB.
-    const int tiles[3][2] = {{8, 8}, {4, 4}, {2, 2}};
-    p.window = 0;
-    for (int t = 0; t < 3; ++t) {
-        if (p.force_tile && tiles[t][0] != p.force_tile) continue;
-        const double rt = 0.5 * std::hypot((tiles[t][0] - 1) * grid->dx, (tiles[t][1] - 1) * grid->dy);
-        const int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
-        const size_t lds = backproject_lds_bytes(p.n_ch, p.block, wl | 1);
-        if ((wl <= (t == 2 ? 128 : 64) && lds <= kMaxLds) || t == 2 || p.force_tile) {
-            p.tile_x = tiles[t][0];
-            p.tile_y = tiles[t][1];
-            p.window = wl;
-            break;
+    // k_z-per-lane kernel tile: the staged range window must hold every tap
+    // of the tile's pixels (|l(p) - l(centre)| <= 2 * half-diagonal).  Prefer
+    // the largest tile whose window fits 64 samples (one staging load per
+    // lane and row; the 2x2 fallback allows 128) and whose LDS (window starts
+    // + two staged windows of 64 x kz_per_lane rows) fits the workgroup's
+    // 160 KiB.
+    if (!p.bp_mfma && !p.bp_gather) {
+        const int tiles[3][2] = {{8, 8}, {4, 4}, {2, 2}};
+        p.window = 0;
+        for (int t = 0; t < 3; ++t) {
+            if (p.force_tile && tiles[t][0] != p.force_tile) continue;
+            const double rt = 0.5 * std::hypot((tiles[t][0] - 1) * grid->dx, (tiles[t][1] - 1) * grid->dy);
+            const int wl = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
+            const size_t lds = backproject_lds_bytes(p.n_ch, p.block, wl | 1);
+            if ((wl <= (t == 2 ? 128 : 64) && lds <= kMaxLds) || t == 2 || p.force_tile) {
+                p.tile_x = tiles[t][0];
+                p.tile_y = tiles[t][1];
+                p.window = wl;
+                break;
+            }
         }
-    }
-    p.waves = p.force_waves ? p.force_waves : 4;
-    if (p.waves == 8 && p.tile_x != 8)
-        return fail(PL_EUNSUPPORTED, "8 wavefronts per workgroup need the 8x8 tile");
-    if (backproject_lds_bytes(p.n_ch, p.block, p.window | 1) > kMaxLds)
-        return fail(PL_EUNSUPPORTED, "back-projection staging exceeds the LDS (lower kz_per_lane)");
+        p.waves = p.force_waves ? p.force_waves : 4;
+        if (p.waves == 8 && p.tile_x != 8)
+            return fail(PL_EUNSUPPORTED, "8 wavefronts per workgroup need the 8x8 tile");
+        if (backproject_lds_bytes(p.n_ch, p.block, p.window | 1) > kMaxLds)
+            return fail(PL_EUNSUPPORTED, "back-projection staging exceeds the LDS (lower kz_per_lane)");
+        p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes
     }
     if (p.window > 128)
         return fail(PL_EUNSUPPORTED, "pixels are too coarse for the range grid (window %d > 128)", p.window);
-    if (!p.bp_mfma) p.window_pad = p.window | 1;  // odd row length: conflict-free LDS reads across lanes
     p.tiles_x = (grid->nx + p.tile_x - 1) / p.tile_x;
     p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
 

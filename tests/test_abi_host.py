@@ -74,7 +74,7 @@ def test_plan_is_consistent(wl):
     assert p.n_kz == wl.array.n_scan
     assert p.n_fine == 2 * p.n_l and p.n_l % 2 == 0
     assert p.kernel_width == 7                      # 1e-6 tolerance
-    assert p.block % 64 == 0
+    assert p.block % 32 == 0
     assert p.n_blocks == math.ceil(wl.array.n_scan / p.block)
     # the range grid covers every channel's range span at the requested step
     arr = ogeom.build(wl.array)
@@ -183,7 +183,7 @@ def test_mfma_backprojection_plan_rules():
         pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=1, kz_block=96)
     assert not pr.hybrid_plan_info(g, fine, precision="fp32").mfma_backprojection
     q = pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=-1)
-    assert not q.mfma_backprojection and q.block == 64
+    assert not q.mfma_backprojection and q.bp_kernel == "pixel-lanes"
     with pytest.raises(pr.PolyreconError) as e:
         pr.hybrid_plan_info(g, fine, precision="fp32", mfma_backprojection=1)
     assert e.value.code == pr.PL_EUNSUPPORTED
@@ -203,3 +203,17 @@ def test_mfma_backprojection_plan_rules():
     assert pr.lib().range_compress(g.handle, C.byref(pr._grid(fine)), C.byref(opts), fake, fake, None, fake,
                                    1 << 40, None) == pr.PL_EUNSUPPORTED
     assert "reconstruct_hybrid" in pr.last_error()
+
+
+def test_valu_backprojection_plan_rules():
+    g = pr.make_geometry(W.C2.array)
+    p = pr.hybrid_plan_info(g, W.C2.grid)
+    assert p.bp_kernel == "pixel-lanes" and p.tile == (8, 8) and p.block == 32 and p.waves == 4
+    assert pr.hybrid_plan_info(g, W.C2.grid, kz_block=64).block == 64
+    assert p.window % 2 == 0 and p.window <= 64
+    assert pr.hybrid_plan_info(g, W.C2.grid, waves=8).bp_kernel == "kz-lanes"
+    assert pr.hybrid_plan_info(g, W.C2.grid, kz_per_lane=1).bp_kernel == "kz-lanes"
+    assert pr.hybrid_plan_info(g, W.C2.grid, tile=4).bp_kernel == "kz-lanes"
+    # pixels too coarse for 64 staged samples: the k_z-per-lane kernel on smaller tiles
+    p1 = pr.hybrid_plan_info(pr.make_geometry(W.C1.array), W.C1.grid)
+    assert p1.bp_kernel == "kz-lanes" and p1.tile == (4, 4)

@@ -284,6 +284,26 @@ def test_hybrid_end_to_end_small(wlname, interp):
     assert rel(img3, img) < 1e-6
 
 
+@pytest.mark.parametrize("case", ["multi-small", "C1"])
+@pytest.mark.parametrize("kernel", ["pixel-lanes", "pixel-lanes-32", "kz-lanes", "kz-lanes-8"])
+def test_valu_backprojection_kernels(case, kernel):
+    # both VALU back-projection layouts on ragged 8x8-tiled grids, FP32 bar
+    wl = {"multi-small": multi_small(), "C1": W.C1}[case]
+    grid = _fine_grid(45, 29, 0.003) if case == "C1" else _fine_grid(27, 35, 0.004)
+    opts = {"pixel-lanes": dict(), "pixel-lanes-32": dict(kz_block=32), "kz-lanes": dict(kz_per_lane=1),
+            "kz-lanes-8": dict(waves=8)}[kernel]
+    g = pr.make_geometry(wl.array)
+    plan = pr.hybrid_plan_info(g, grid, **opts)
+    assert plan.bp_kernel == kernel.replace("-8", "").replace("-32", "")
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 47)
+    say("valu back-projection", case, kernel, plan.tile, plan.window)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), **opts))
+    err = rel(img, ohyb.image(arr, grid, s))
+    say("   rel L2", err)
+    assert err < 1e-4
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (9, 13), (17, 5), (64, 40)])
 def test_hybrid_ragged_grids(nx, ny):
     wl = W.tiny("multi")
