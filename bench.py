@@ -29,6 +29,27 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
 
 
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per back-projection launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
+    kernel and workload or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "backproject_c2_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("traffic:"):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split()[1:])
+        if (f.get("kernel"), f.get("workload"), f.get("precision")) != (kernel, workload, precision):
+            continue
+        src = os.path.join(ROOT, f["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
+            return None
+        return int(f["fetch_bytes"]) + int(f["write_bytes"])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -214,8 +235,9 @@ def main() -> int:
         "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
                    "tile": list(plan.tile), "kz_block": plan.block},
-        "roofline": dict(roof, unit="TFLOP/s", traffic=None, kernel="backproject",
-                         flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
+        "roofline": dict(roof, unit="TFLOP/s",
+                         traffic=measured_traffic(plan.bp_kernel, args.config, args.precision),
+                         kernel="backproject", flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
         "stages_ms": stage,
         "plan_build_ms": first_ms,
     }

@@ -183,18 +183,31 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
         if (c < a.n_ch) {
             const float sc = ldexpf(1.f, -se[static_cast<size_t>(kap) * a.n_chp + c]);
             if constexpr (SPLIT) {
+                // four consecutive rows per lane and plane: one 8-byte store
+                // each (n_l is a multiple of 4)
                 unsigned short* dst =
                     static_cast<unsigned short*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 4 * a.n_l;
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int r = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
+                for (int g = 0; g < 4; ++g) {
+                    const int r = row0 + 8 * g + 4 * (lane >> 5);
                     if (r < a.n_l) {
-                        const float xr = accr[v] * sc, xi = acci[v] * sc;
-                        const unsigned short rh = bf16_of(xr), ih = bf16_of(xi);
-                        dst[r] = rh;
-                        dst[a.n_l + r] = bf16_of(xr - __uint_as_float(static_cast<unsigned>(rh) << 16));
-                        dst[2 * a.n_l + r] = ih;
-                        dst[3 * a.n_l + r] = bf16_of(xi - __uint_as_float(static_cast<unsigned>(ih) << 16));
+                        unsigned short rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float xr = accr[4 * g + k] * sc, xi = acci[4 * g + k] * sc;
+                            rh[k] = bf16_of(xr);
+                            ih[k] = bf16_of(xi);
+                            rl[k] = bf16_of(xr - __uint_as_float(static_cast<unsigned>(rh[k]) << 16));
+                            il[k] = bf16_of(xi - __uint_as_float(static_cast<unsigned>(ih[k]) << 16));
+                        }
+                        auto pack = [](const unsigned short (&h)[4]) {
+                            return make_uint2(h[0] | (static_cast<unsigned>(h[1]) << 16),
+                                              h[2] | (static_cast<unsigned>(h[3]) << 16));
+                        };
+                        *reinterpret_cast<uint2*>(dst + r) = pack(rh);
+                        *reinterpret_cast<uint2*>(dst + a.n_l + r) = pack(rl);
+                        *reinterpret_cast<uint2*>(dst + 2 * a.n_l + r) = pack(ih);
+                        *reinterpret_cast<uint2*>(dst + 3 * a.n_l + r) = pack(il);
                     }
                 }
             } else {
@@ -254,6 +267,7 @@ int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws
 int launch_range_compress_mfma_split(const HybridPlan& p, const float2* spec, char* ws, unsigned short* qs,
                                      hipStream_t s) {
     if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
+    if (p.n_l % 4) return fail(PL_EUNSUPPORTED, "split range profiles need n_l divisible by 4");
     return p.precision == PL_PREC_FP16 ? run_mfma<true, true>(p, spec, ws, qs, s) : run_mfma<false, true>(p, spec, ws, qs, s);
 }
 

@@ -147,6 +147,8 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
             return fail(PL_EINVAL, "MFMA back-projection tiles are 8x8, 16x8 or 16x16");
         const int kb = p.force_kb ? p.force_kb : 64;
         if (kb == 32) return fail(PL_EINVAL, "the MFMA back-projection takes 64 or 128 k_z bins per workgroup");
+        // eight wavefronts (two 4x4 groups each) on the 16x16 and 16x8 tiles
+        // with 64 k_z bins: measured fastest on gfx950
         const double gdiag = std::hypot(3.0 * grid->dx, 3.0 * grid->dy);
         set_blocks(kb, p.sigma_l);
         if (std::ceil(2.0 * gdiag / p.du) > 9) {
@@ -166,7 +168,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
             p.tile_y = ty;
             p.window = 8 * nck;  // samples staged per plane and row
             p.window_pad = 33;   // LDS row length in 16-byte chunks (4 planes x 8 + 1)
-            p.waves = p.force_waves ? p.force_waves : 4;
+            p.waves = p.force_waves ? p.force_waves : ((tx * ty >= 128 && kb == 64) ? 8 : 4);
             if (tx * ty == 64 && p.waves == 8)
                 return fail(PL_EUNSUPPORTED, "8 wavefronts need a 16x8 or 16x16 MFMA tile");
             if (tx * ty == 256 && kb == 128 && p.waves == 8)
@@ -261,10 +263,12 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.tiles_x = (grid->nx + p.tile_x - 1) / p.tile_x;
     p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
 
+    // range samples: a multiple of 4 (8-byte stores of split BF16 profiles)
+    // with a 2,3,5-smooth fine grid of 2 n_l
     int nl = static_cast<int>(std::ceil(span / p.du)) + 8;
     nl = std::max(nl, p.window + 2);
-    nl += nl & 1;
-    while (!is_fft_friendly(2 * nl)) nl += 2;
+    nl = (nl + 3) & ~3;
+    while (!is_fft_friendly(2 * nl)) nl += 4;
     p.n_l = nl;
     p.n_fine = 2 * nl;
     if (p.n_fine > kMaxFine)
