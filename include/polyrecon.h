@@ -326,6 +326,39 @@ int backproject(const pl_geometry* geom, const pl_image_grid* grid, const pl_hyb
 int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spectrum_dev,
             float* image_dev, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batches */
+/*
+ * Several scans (each its own geometry, scan length, frequency count and
+ * image grid) reconstructed by one call, each exactly as reconstruct_hybrid
+ * would (same plan, same result).  The per-scan steps are launched per scan;
+ * the back-projection of every scan whose plan takes the pixel-per-lane
+ * kernel (PL_BP_PIXEL_LANES, with the k_z block size of the first such scan)
+ * runs in one persistent launch per LDS row length (at most 8) that takes
+ * (scan, k_z block, pixel tile) work items from device-side queues, one per
+ * XCD with stealing, heaviest scans first; other scans' back-projections
+ * follow as their own launches.
+ *
+ * make_hybrid_batch plans the n scans (opts: an array of n, or NULL for the
+ * defaults), and uploads the work queue to the current device (a small
+ * allocation owned by the batch; use the batch on that device only).
+ * reconstruct_hybrid_batch takes arrays of n device pointers: echoes
+ * ([c][m][f] complex64 per scan) and images ([z][y][x] complex64 per scan),
+ * and a 256-byte-aligned device workspace of hybrid_batch_info's size.  It
+ * allocates nothing and does not synchronise, so it may be captured in a
+ * graph; calls sharing one workspace must not overlap.
+ * hybrid_batch_info: workspace bytes, scans in the persistent launch, its
+ * work items and workgroups (any pointer may be NULL).
+ * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.
+ */
+typedef struct pl_hybrid_batch pl_hybrid_batch; /* opaque */
+int make_hybrid_batch(int32_t n, const pl_geometry* const* geoms, const pl_image_grid* grids,
+                      const pl_hybrid_opts* opts, pl_hybrid_batch** batch);
+int destroy_hybrid_batch(pl_hybrid_batch* batch);
+int hybrid_batch_info(const pl_hybrid_batch* batch, size_t* workspace_bytes, int32_t* queued_scans,
+                      int32_t* work_items, int32_t* workgroups);
+int reconstruct_hybrid_batch(const pl_hybrid_batch* batch, const float* const* echoes_dev,
+                             float* const* images_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* -------------------------------------------------------- back-projection */
 /*
  * Brute-force back-projection (the paper's comparison method; its formula is

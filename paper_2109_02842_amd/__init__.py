@@ -95,6 +95,11 @@ _SIGNATURES = {
     "bp_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "reconstruct_bp": (C.c_int, [_P, C.POINTER(ImageGridC), C.c_int32, C.c_int32, _P, _P, _P,
                                  C.c_size_t, _P]),
+    "make_hybrid_batch": (C.c_int, [C.c_int32, _P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), C.POINTER(_P)]),
+    "destroy_hybrid_batch": (C.c_int, [_P]),
+    "hybrid_batch_info": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
+    "reconstruct_hybrid_batch": (C.c_int, [_P, _P, _P, _P, C.c_size_t, _P]),
     "last_error": (C.c_char_p, []),
 }
 EXPORTED = tuple(_SIGNATURES)
@@ -337,6 +342,91 @@ def reconstruct_hybrid(geom: Geometry, grid, echo, out=None, ws=None, **opts):
                                     _dev_c64(echo, geom.echo_shape, "echo"), _dev_c64(out, shape, "out"),
                                     C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
+
+
+# ------------------------------------------------------------------ batches
+class HybridBatch:
+    """Owning wrapper of a ``pl_hybrid_batch*``: several scans reconstructed by
+    one call, their back-projections in one persistent launch.
+
+    ``opts`` is one dict of options for every scan or a list of dicts."""
+
+    def __init__(self, geoms, grids, opts=None):
+        n = len(geoms)
+        if len(grids) != n:
+            raise ValueError("one grid per geometry")
+        if opts is None or isinstance(opts, dict):
+            opts = [dict(opts or {})] * n
+        if len(opts) != n:
+            raise ValueError("one options dict per geometry")
+        self.geoms, self.grids, self.opts = list(geoms), list(grids), [dict(o) for o in opts]
+        handles = (_P * n)(*[g.handle for g in geoms])
+        cgrids = (ImageGridC * n)(*[_grid(g) for g in grids])
+        copts = (HybridOpts * n)(*[_opts(**o) for o in opts])
+        h = _P()
+        _check(lib().make_hybrid_batch(n, C.cast(handles, _P), cgrids, copts, C.byref(h)))
+        self.handle = h
+        ws, queued, items, wgs = C.c_size_t(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().hybrid_batch_info(h, C.byref(ws), C.byref(queued), C.byref(items), C.byref(wgs)))
+        self.workspace_bytes = int(ws.value)
+        self.queued_scans, self.work_items, self.workgroups = queued.value, items.value, wgs.value
+
+    def __len__(self):
+        return len(self.geoms)
+
+    def image_shape(self, i):
+        return (self.geoms[i].n_scan, self.grids[i].ny, self.grids[i].nx)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().destroy_hybrid_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct_hybrid_batch(batch: HybridBatch, echoes, outs=None, ws=None):
+    """Images of every scan of ``batch`` (list of complex64 device tensors)."""
+    torch = _torch()
+    n = len(batch)
+    if len(echoes) != n:
+        raise ValueError(f"{n} echoes expected")
+    ws = _ws(ws, batch.workspace_bytes)
+    if outs is None:
+        outs = [torch.empty(batch.image_shape(i), dtype=torch.complex64, device=echoes[i].device) for i in range(n)]
+    e_ptrs = (_P * n)(*[_dev_c64(echoes[i], batch.geoms[i].echo_shape, f"echo {i}") for i in range(n)])
+    o_ptrs = (_P * n)(*[_dev_c64(outs[i], batch.image_shape(i), f"out {i}") for i in range(n)])
+    _check(lib().reconstruct_hybrid_batch(batch.handle, C.cast(e_ptrs, _P), C.cast(o_ptrs, _P),
+                                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return outs
+
+
+class CapturedBatch:
+    """A batch call captured once in a graph (torch.cuda.CUDAGraph) and
+    replayed: the echo and image tensors and the workspace are fixed at
+    capture; copy new echoes into ``echoes`` before ``replay()``."""
+
+    def __init__(self, batch: HybridBatch, echoes):
+        torch = _torch()
+        self.batch = batch
+        self.echoes = [e.clone() for e in echoes]
+        self.ws = workspace(batch.workspace_bytes)
+        self.outs = [torch.empty(batch.image_shape(i), dtype=torch.complex64, device="cuda")
+                     for i in range(len(batch))]
+        # one eager call first (lazily created device tables, kernel attributes)
+        reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws)
+
+    def replay(self):
+        self.graph.replay()
+        return self.outs
 
 
 STAGES = ("plan_tables", "scan_fft", "range_compress", "backproject", "kz_ifft")

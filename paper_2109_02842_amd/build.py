@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libpolyrecon.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = "gfx950"
 
-SOURCES = ["geometry.cpp", "plan.cpp", "api.cpp", "k_fft.hip", "k_nufft.hip", "k_backproject.hip",
+SOURCES = ["geometry.cpp", "plan.cpp", "api.cpp", "batch.cpp", "k_fft.hip", "k_nufft.hip", "k_backproject.hip",
            "k_simulate.hip", "k_mfma.hip", "k_backproject_mfma.hip"]
 
 CFLAGS = [

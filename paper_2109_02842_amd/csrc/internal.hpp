@@ -102,6 +102,17 @@ struct HybridPlan {
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 size_t backproject_mfma_lds_bytes(int n_ch, int kz_block);
 size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks);
+
+// Batched pixel-per-lane back-projection (one persistent launch for several
+// scans): a per-scan descriptor of gather_batch_desc_bytes() bytes, built on
+// the host; work items are int4 (scan, k_z block, tile, 0) in eight
+// contiguous per-XCD queues delimited by bounds[0..8] (device ints); eight
+// counters (unsigned) live in the caller's workspace.
+size_t gather_batch_desc_bytes();
+int build_gather_batch_desc(const HybridPlan& p, const double* chan, size_t ws_off, int rsc, void* out);
+int gather_batch_grid(int kb, int rsc, size_t smem, int* blocks);
+int launch_gather_batch(const void* descs, const void* items, const int* bounds, unsigned* counters, char* ws,
+                        int kb, int rsc, size_t smem, int blocks, hipStream_t s);
 int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
               HybridPlan* p);
 

@@ -15,6 +15,8 @@
 // the load latency), one barrier per channel.  Blocks are assigned so that each XCD
 // works on a contiguous range of (k_z block, tile) work items, which keeps
 // the range profiles it reads in its own L2.
+#include <cstring>
+
 #include "device.hpp"
 
 namespace pl {
@@ -257,6 +259,14 @@ struct BpgArgs {
     double kref[kMaxBlocks];
 };
 
+// One scan of a batch: its arguments, channel table, and byte offsets of its
+// range profiles, range origins and spectrum in the batch workspace.
+struct BatchScanDesc {
+    BpgArgs a;
+    const double* chan;
+    unsigned long long q_off, llo_off, g_off;
+};
+
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PL_DMA16(SRC, DST) __builtin_amdgcn_global_load_lds((SRC), (DST), 16, 0, 0)
 #else
@@ -268,23 +278,19 @@ constexpr int kGatherBatch = 4;   // channels per weight batch
 
 // RSC 16-byte chunks per LDS row, of which nchk are staged: the window's
 // chunks and one more, since a pixel may read one chunk past its last tap.
+// One (k_z block, tile) work item; smem = the workgroup's LDS (win_bytes of
+// window starts, then the weight slots, then the two row buffers).
 template <int KB, int RSC>
-__global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(const float2* __restrict__ q,
-                                                                               const double* __restrict__ chan,
-                                                                               const double* __restrict__ llo,
-                                                                               BpgArgs a, float2* __restrict__ G) {
+__device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __restrict__ q,
+                                            const double* __restrict__ chan, const double* __restrict__ llo,
+                                            float2* __restrict__ G, int blk, int tile, unsigned char* smem) {
     constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
     constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
     constexpr unsigned kBufBytes = KB * RSC * 16;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int* win = reinterpret_cast<int*>(smem);
     float4* wts = reinterpret_cast<float4*>(smem + a.win_bytes);   // [2][NB][2][64]
     const unsigned lds_q = static_cast<unsigned>(a.win_bytes + 2 * NB * 2 * 64 * 16);
 
-    const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
-    const int blk = work / a.n_tiles;
-    const int tile = work - blk * a.n_tiles;
     const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -419,6 +425,54 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(c
 #undef PL_DMA16
 
 template <int KB, int RSC>
+__global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(const float2* __restrict__ q,
+                                                                               const double* __restrict__ chan,
+                                                                               const double* __restrict__ llo,
+                                                                               BpgArgs a, float2* __restrict__ G) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
+    const int blk = work / a.n_tiles;
+    gather_tile<KB, RSC>(a, q, chan, llo, G, blk, work - blk * a.n_tiles, smem);
+}
+
+// Persistent form for a batch of scans: eight work queues, one per XCD, each
+// a contiguous range [bounds[x], bounds[x+1]) of (scan, k_z block, tile)
+// items (cost-balanced, heaviest scans first) with an atomic counter.  A
+// workgroup takes items from its own XCD's queue (so an XCD's L2 sees a
+// compact set of range profiles) and, once it is empty, from the others in
+// turn; it leaves after all eight are exhausted.
+template <int KB, int RSC>
+__global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_batch_kernel(
+    const BatchScanDesc* __restrict__ scans, const int4* __restrict__ items, const int* __restrict__ bounds,
+    unsigned* __restrict__ counters, char* __restrict__ ws) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int next;
+    const int home = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int x = (home + k) & 7;
+        const int lo = bounds[x], hi = bounds[x + 1];
+        for (;;) {
+            if (threadIdx.x == 0) next = lo + static_cast<int>(atomicAdd(counters + x, 1u));
+            __syncthreads();
+            const int it = next;
+            __syncthreads();  // every thread has read `next` before it is overwritten
+            if (it >= hi) break;
+            const int4 w = items[it];
+            const BatchScanDesc& d = scans[w.x];
+            gather_tile<KB, RSC>(d.a, reinterpret_cast<const float2*>(ws + d.q_off), d.chan,
+                                 reinterpret_cast<const double*>(ws + d.llo_off),
+                                 reinterpret_cast<float2*>(ws + d.g_off), w.y, w.z, smem);
+            __syncthreads();  // LDS is reused by the next item
+        }
+    }
+}
+
+__global__ void reset_counters_kernel(unsigned* c) {
+    if (threadIdx.x < 8) c[threadIdx.x] = 0u;
+}
+
+template <int KB, int RSC>
 int launch_gather(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
                   const double* chan, const double* llo, float2* G) {
     auto fn = backproject_gather_kernel<KB, RSC>;
@@ -431,7 +485,7 @@ int launch_gather(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s,
     return check_launch("back-projection (pixel per lane)");
 }
 
-int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws, float2* G, hipStream_t s) {
+BpgArgs gather_args(const HybridPlan& p) {
     BpgArgs a{};
     a.n_ch = p.n_ch;
     a.n_z = p.n_z;
@@ -453,9 +507,35 @@ int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, cha
     for (int k = 0; k < 4; ++k)
         for (int j = 0; j < 4; ++j) a.coef[k][j] = p.coef[k][j];
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
-    if ((p.block != 32 && p.block != 64) || p.tile_x != 8 || p.tile_y != 8 || p.window % 2 || a.nchk < 3 ||
-        a.nchk > p.window_pad || 2 * a.nchk > p.n_l || p.waves != kGatherWaves)
+    return a;
+}
+
+int check_gather_plan(const HybridPlan& p, int rsc) {
+    const int nchk = p.window / 2 + 1;
+    if (!p.bp_gather || (p.block != 32 && p.block != 64) || p.tile_x != 8 || p.tile_y != 8 || p.window % 2 ||
+        nchk < 3 || nchk > p.window_pad || p.window_pad > rsc || 2 * nchk > p.n_l || p.waves != kGatherWaves)
         return fail(PL_EUNSUPPORTED, "pixel-per-lane back-projection: window %d, block %d", p.window, p.block);
+    return PL_OK;
+}
+
+template <int KB, int RSC>
+const void* gather_batch_fn() {
+    return reinterpret_cast<const void*>(backproject_gather_batch_kernel<KB, RSC>);
+}
+
+const void* gather_batch_kernel(int kb, int rsc) {
+#define PL_GB(KB, RSC) \
+    if (kb == KB && rsc == RSC) return gather_batch_fn<KB, RSC>();
+    PL_GB(64, 12) PL_GB(64, 16) PL_GB(64, 20) PL_GB(64, 24) PL_GB(64, 33)
+    PL_GB(32, 12) PL_GB(32, 16) PL_GB(32, 20) PL_GB(32, 24) PL_GB(32, 33)
+#undef PL_GB
+    return nullptr;
+}
+
+int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, char* ws, float2* G, hipStream_t s) {
+    const BpgArgs a = gather_args(p);
+    int rc = check_gather_plan(p, p.window_pad);
+    if (rc) return rc;
     const size_t smem = backproject_gather_lds_bytes(p.n_ch, p.block, p.window_pad);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
@@ -469,6 +549,60 @@ int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, cha
 }
 
 }  // namespace
+
+size_t gather_batch_desc_bytes() { return sizeof(BatchScanDesc); }
+
+int build_gather_batch_desc(const HybridPlan& p, const double* chan, size_t ws_off, int rsc, void* out) {
+    int rc = check_gather_plan(p, rsc);
+    if (rc) return rc;
+    BatchScanDesc d{};
+    d.a = gather_args(p);
+    d.chan = chan;
+    d.q_off = ws_off + p.off_q;
+    d.llo_off = ws_off + p.off_llo;
+    d.g_off = ws_off + p.off_G;
+    std::memcpy(out, &d, sizeof(d));
+    return PL_OK;
+}
+
+int gather_batch_grid(int kb, int rsc, size_t smem, int* blocks) {
+    const void* fn = gather_batch_kernel(kb, rsc);
+    if (!fn) return fail(PL_EUNSUPPORTED, "no batched back-projection for %d k_z bins, %d-chunk rows", kb, rsc);
+    if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "batched back-projection needs %zu bytes of LDS", smem);
+    if (smem > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem)) !=
+                            hipSuccess)
+        return fail(PL_EDEVICE, "batched back-projection: LDS of %zu bytes refused", smem);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kGatherWaves, smem) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(PL_EDEVICE, "batched back-projection: occupancy query failed");
+    // Workgroups beyond the resident ones start only once the queues are
+    // empty and leave at once, so size the grid by the LDS bound too.
+    const int by_lds = static_cast<int>(kMaxLds / (smem + 256));
+    *blocks = (std::max(1, std::max(per_cu, std::min(by_lds, 8))) * cus + 7) & ~7;
+    return PL_OK;
+}
+
+int launch_gather_batch(const void* descs, const void* items, const int* bounds, unsigned* counters, char* ws,
+                        int kb, int rsc, size_t smem, int blocks, hipStream_t s) {
+    const void* fn = gather_batch_kernel(kb, rsc);
+    if (!fn) return fail(PL_EUNSUPPORTED, "no batched back-projection for %d k_z bins, %d-chunk rows", kb, rsc);
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, counters);
+    int rc = check_launch("batch work counters");
+    if (rc) return rc;
+    auto args_descs = static_cast<const BatchScanDesc*>(descs);
+    auto args_items = static_cast<const int4*>(items);
+#define PL_GB(KB, RSC)                                                                                          \
+    if (kb == KB && rsc == RSC) {                                                                               \
+        hipLaunchKernelGGL((backproject_gather_batch_kernel<KB, RSC>), dim3(blocks), dim3(64 * kGatherWaves), smem, \
+                           s, args_descs, args_items, bounds, counters, ws);                                    \
+        return check_launch("batched back-projection");                                                         \
+    }
+    PL_GB(64, 12) PL_GB(64, 16) PL_GB(64, 20) PL_GB(64, 24) PL_GB(64, 33)
+    PL_GB(32, 12) PL_GB(32, 16) PL_GB(32, 20) PL_GB(32, 24) PL_GB(32, 33)
+#undef PL_GB
+    return fail(PL_EUNSUPPORTED, "no batched back-projection for %d k_z bins, %d-chunk rows", kb, rsc);
+}
 
 size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks) {
     return static_cast<size_t>((n_ch + 3) & ~3) * 4 + 2ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;

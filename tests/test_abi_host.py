@@ -217,3 +217,25 @@ def test_valu_backprojection_plan_rules():
     # pixels too coarse for 64 staged samples: the k_z-per-lane kernel on smaller tiles
     p1 = pr.hybrid_plan_info(pr.make_geometry(W.C1.array), W.C1.grid)
     assert p1.bp_kernel == "kz-lanes" and p1.tile == (4, 4)
+
+
+def test_batch_argument_errors_before_device_use():
+    import ctypes as C
+    L = pr.lib()
+    h = C.c_void_p()
+    assert L.make_hybrid_batch(0, None, None, None, C.byref(h)) == pr.PL_EINVAL
+    assert L.make_hybrid_batch(2, None, None, None, C.byref(h)) == pr.PL_EINVAL
+    assert L.make_hybrid_batch(1, None, None, None, None) == pr.PL_EINVAL
+    assert L.hybrid_batch_info(None, None, None, None, None) == pr.PL_EINVAL
+    assert L.reconstruct_hybrid_batch(None, None, None, None, 0, None) == pr.PL_EINVAL
+    assert L.destroy_hybrid_batch(None) == pr.PL_OK
+
+
+def test_batch_c5_workload():
+    wls = W.batch_c5()
+    assert len(wls) == 16 and len({w.name for w in wls}) == 16
+    for w in wls:
+        a = w.array
+        assert 3 <= a.n_chords <= 7 and 32 <= a.n_elem <= 64 and 32 <= a.n_freq <= 128
+        assert 128 <= a.n_scan <= 512 and pr.hybrid_plan_info(pr.make_geometry(a), w.grid).bp_kernel == "pixel-lanes"
+    assert W.batch_c5()[3] == wls[3]           # seeded

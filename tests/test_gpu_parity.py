@@ -414,3 +414,87 @@ def test_binding_rejects_bad_tensors():
         pr.reconstruct_hybrid(g, wl.grid, s[:, :5].contiguous())
     with pytest.raises(TypeError):
         pr.reconstruct_hybrid(g, wl.grid, s.cpu())
+
+
+# ------------------------------------------------------------------ batches
+def _small_batch():
+    """Uneven scans: pixel-per-lane scans of different sizes, one whose pixels
+    are too coarse for it (k_z-per-lane kernel), one BF16 scan on the matrix
+    cores; every kind of back-projection the batch call launches."""
+    c1 = W.C1
+    ms = multi_small()
+    scans = [
+        (c1.array, _fine_grid(45, 29, 0.003), {}),
+        (replace(c1.array, n_scan=30, n_freq=20), _fine_grid(21, 40, 0.004), {}),
+        (ms.array, _fine_grid(27, 35, 0.004), {}),
+        (c1.array, c1.grid, {}),                                              # coarse: k_z per lane
+        (replace(c1.array, n_scan=32), _fine_grid(40, 40, 0.0015), dict(precision="bf16", mfma_backprojection=1)),
+    ]
+    return scans
+
+
+def test_batch_matches_single_scans():
+    scans = _small_batch()
+    geoms = [pr.make_geometry(a) for a, _, _ in scans]
+    batch = pr.HybridBatch(geoms, [g for _, g, _ in scans], [o for _, _, o in scans])
+    say("batch", len(batch), "queued", batch.queued_scans, "items", batch.work_items, "workgroups", batch.workgroups)
+    assert batch.queued_scans == 3
+    echoes = [dev(W.random_echo(a, 60 + i)) for i, (a, _, _) in enumerate(scans)]
+    outs = pr.reconstruct_hybrid_batch(batch, echoes)
+    for i, ((a, grid, o), g) in enumerate(zip(scans, geoms)):
+        single = host(pr.reconstruct_hybrid(g, grid, echoes[i], **o))
+        got = host(outs[i])
+        err = rel(got, single)
+        say("   scan", i, "batch vs single", err)
+        assert err == 0.0, i      # same kernels, same arithmetic
+    # and the oracle for one queued scan
+    a, grid, _ = scans[1]
+    ref = ohyb.image(ogeom.build(a), grid, W.random_echo(a, 61))
+    assert rel(host(outs[1]), ref) < 1e-4
+
+
+def test_batch_c5_against_oracle():
+    wls = W.batch_c5()
+    geoms = [pr.make_geometry(w.array) for w in wls]
+    batch = pr.HybridBatch(geoms, [w.grid for w in wls])
+    say("C5 batch: queued", batch.queued_scans, "items", batch.work_items, "workgroups", batch.workgroups)
+    assert batch.queued_scans == len(wls)
+    echoes = [dev(W.random_echo(w.array, 70 + i)) for i, w in enumerate(wls)]
+    outs = pr.reconstruct_hybrid_batch(batch, echoes)
+    for i in (0, 7, 15):
+        w = wls[i]
+        img = host(outs[i])
+        assert np.all(np.isfinite(img))
+        npix = w.grid.nx * w.grid.ny
+        kap = sorted(set(W.random_subset(w.array.n_scan, 2, 80 + i).tolist() + [0]))
+        pix = W.random_subset(npix, 96, 90 + i)
+        px, py = ohyb.pixel_grid(w.grid)
+        ref = ohyb.spectrum_at(ogeom.build(w.array), ohyb.scan_spectrum(W.random_echo(w.array, 70 + i)), kap,
+                               px[pix], py[pix])
+        err = rel(_spectrum_subset(img, kap, pix), ref)
+        say("   scan", i, w.name, "rel L2", err)
+        assert err < 1e-4
+
+
+def test_batch_graph_replays():
+    scans = _small_batch()[:3]
+    geoms = [pr.make_geometry(a) for a, _, _ in scans]
+    batch = pr.HybridBatch(geoms, [g for _, g, _ in scans])
+    e1 = [dev(W.random_echo(a, 100 + i)) for i, (a, _, _) in enumerate(scans)]
+    e2 = [dev(W.random_echo(a, 200 + i)) for i, (a, _, _) in enumerate(scans)]
+    eager1 = [host(t) for t in pr.reconstruct_hybrid_batch(batch, e1)]
+    eager2 = [host(t) for t in pr.reconstruct_hybrid_batch(batch, e2)]
+    cap = pr.CapturedBatch(batch, e1)
+    for rep in range(4):
+        src = e1 if rep % 2 == 0 else e2
+        want = eager1 if rep % 2 == 0 else eager2
+        for dst, e in zip(cap.echoes, src):
+            dst.copy_(e)
+        outs = cap.replay()
+        got = [host(t) for t in outs]
+        # eager work between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        for i in range(len(scans)):
+            assert rel(got[i], want[i]) == 0.0, (rep, i)
+        del junk
