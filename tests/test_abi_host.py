@@ -239,3 +239,26 @@ def test_batch_c5_workload():
         assert 3 <= a.n_chords <= 7 and 32 <= a.n_elem <= 64 and 32 <= a.n_freq <= 128
         assert 128 <= a.n_scan <= 512 and pr.hybrid_plan_info(pr.make_geometry(a), w.grid).bp_kernel == "pixel-lanes"
     assert W.batch_c5()[3] == wls[3]           # seeded
+
+
+def test_autotune_candidates_and_cache(tmp_path):
+    from paper_2109_02842_amd import autotune as at
+    g = pr.make_geometry(W.C2.array)
+    c32 = at.candidates(g, W.C2.grid, "fp32")
+    kernels = {(pr.hybrid_plan_info(g, W.C2.grid, **o).bp_kernel, pr.hybrid_plan_info(g, W.C2.grid, **o).block)
+               for o in c32}
+    assert ("pixel-lanes", 32) in kernels and ("pixel-lanes", 64) in kernels and ("kz-lanes", 64) in kernels
+    assert not any(o.get("mfma_backprojection") for o in c32)
+    cb = at.candidates(g, W.C2.grid, "bf16")
+    assert any(o.get("mfma_backprojection") for o in cb) and len(cb) > len(c32)
+    # coarse pixels: every request maps to the k_z-per-lane kernel, listed once per shape
+    g1 = pr.make_geometry(W.C1.array)
+    c1 = at.candidates(g1, W.C1.grid, "fp32")
+    shapes = [(p.bp_kernel, p.tile, p.block, p.waves) for p in (pr.hybrid_plan_info(g1, W.C1.grid, **o) for o in c1)]
+    assert len(shapes) == len(set(shapes)) and all(s[0] == "kz-lanes" for s in shapes)
+    # a cached entry is returned without timing anything
+    cache = str(tmp_path / "tune.json")
+    key = at.signature(g, W.C2.grid, "fp32", {}) + "|" + at._device_name()
+    at._store(cache, {key: {"best": {"precision": "fp32", "kz_block": 64}, "times": {"x": 1.0}}})
+    best, times = at.autotune(g, W.C2.grid, "fp32", cache=cache)
+    assert best == {"precision": "fp32", "kz_block": 64} and times == {"x": 1.0}

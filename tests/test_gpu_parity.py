@@ -498,3 +498,18 @@ def test_batch_graph_replays():
         for i in range(len(scans)):
             assert rel(got[i], want[i]) == 0.0, (rep, i)
         del junk
+
+
+def test_autotune_picks_a_valid_configuration(tmp_path):
+    from paper_2109_02842_amd import autotune as at
+    wl = W.C1
+    grid = _fine_grid(45, 29, 0.003)
+    g = pr.make_geometry(wl.array)
+    cache = str(tmp_path / "tune.json")
+    best, times = at.autotune(g, grid, "bf16", cache=cache, repeats=2)
+    say("autotune", best, "of", len(times), "candidates")
+    assert len(times) == len(at.candidates(g, grid, "bf16")) and min(times.values()) > 0
+    s = W.random_echo(wl.array, 48)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), **best))
+    assert rel(img, ohyb.image(ogeom.build(wl.array), grid, s)) < 1e-3
+    assert at.autotune(g, grid, "bf16", cache=cache) == (best, times)     # cached
