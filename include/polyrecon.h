@@ -297,6 +297,24 @@ int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid
                               float* image_dev, void* ws, size_t ws_bytes,
                               hipEvent_t* stage_events, hipStream_t stream);
 
+/*
+ * Adjoint of the imaging operator: image_dev ([z][y][x] complex64) ->
+ * echo_dev ([c][m][f] complex64), the exact conjugate transpose of the
+ * linear map echo -> image that reconstruct_hybrid evaluates (with the range
+ * compression's sum taken exactly instead of by NUFFT): the forward transform
+ * over z with 1/n_z, the scatter form of the back-projection (eq. 8b/19b
+ * transposed: each pixel's interpolation taps times the conjugate carrier),
+ * the direct type-2 sum over the range grid (eq. 8a/19a transposed) and the
+ * unnormalised inverse transform over k_z.  It serves as the echo model of
+ * least-squares refinement (scene image -> echo).  FP32 plans with the
+ * pixel-per-lane back-projection only (PL_EUNSUPPORTED otherwise); the same
+ * workspace size as reconstruct_hybrid.  The back-projection adjoint adds
+ * with float atomics, so results agree between runs to rounding, not bitwise.
+ * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.
+ */
+int adjoint_hybrid(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                   const float* image_dev, float* echo_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------- the hybrid steps alone */
 /*
  * The four steps of reconstruct_hybrid as separate calls, for inspection and

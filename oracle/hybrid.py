@@ -110,3 +110,32 @@ def spectrum(arr, grid, echo, kappas=None):
 def image(arr, grid, echo):
     """g[z][y][x]: inverse FFT over k_z of the full spectrum (eq. 9)."""
     return np.fft.ifft(spectrum(arr, grid, echo), axis=0)
+
+
+def image_adjoint(arr, grid, g):
+    """Adjoint of `image`: the echo-shaped s~[c][m][f] with
+    <image(s), g> = <s, image_adjoint(g)> for every echo s and image g.
+
+    `image` is s -> S = fft over m (unnormalised) -> G[kappa, p] =
+    sum_c sum_f k_f S[c,kappa,f] exp(+j k_rho l_c(p)) -> g = ifft over kappa.
+    Its adjoint takes the steps in reverse with conjugate phases: the adjoint
+    of numpy's ifft (1/N sum exp(+j..)) is fft / N, the adjoint of the
+    element-and-frequency sum is S~[c,kappa,f] = k_f sum_p exp(-j k_rho l_c(p))
+    G~[kappa,p] (evanescent terms dropped as in the forward), and the adjoint
+    of the unnormalised fft is N ifft.  Used as the echo model of the
+    least-squares refinement (the forward model taken as the adjoint of the
+    imaging operator).
+    """
+    n_z = arr.z_scan.size
+    px, py = pixel_grid(grid)
+    g = np.asarray(g, dtype=np.complex128).reshape(n_z, px.size)
+    Gt = np.fft.fft(g, axis=0) / n_z
+    kz = kz_grid(n_z, arr.scan_step)
+    l = range_of(arr, px, py)                      # (n_ch, P)
+    St = np.zeros((l.shape[0], n_z, arr.k.size), dtype=np.complex128)
+    for kap in range(n_z):
+        krho, valid = dispersion(arr.mode, arr.k, kz[kap])
+        w = arr.k * valid
+        for c in range(l.shape[0]):
+            St[c, kap, :] = w * (np.exp(-1j * np.outer(krho, l[c])) @ Gt[kap])
+    return np.fft.ifft(St, axis=1) * n_z

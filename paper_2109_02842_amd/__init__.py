@@ -84,6 +84,8 @@ _SIGNATURES = {
                                          C.POINTER(C.c_size_t)]),
     "reconstruct_hybrid": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                                      C.c_size_t, _P]),
+    "adjoint_hybrid": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
+                                 C.c_size_t, _P]),
     "reconstruct_hybrid_events": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P,
                                             _P, C.c_size_t, _P, _P]),
     "scan_fft": (C.c_int, [_P, _P, _P, _P]),
@@ -427,6 +429,21 @@ class CapturedBatch:
     def replay(self):
         self.graph.replay()
         return self.outs
+
+
+def adjoint_hybrid(geom: Geometry, grid, image, out=None, ws=None, **opts):
+    """Echo-shaped s~[c][m][f] = H^H g: the adjoint of reconstruct_hybrid's
+    linear map (FP32 pixel-per-lane plans)."""
+    torch = _torch()
+    need = hybrid_workspace_bytes(geom, grid, **opts)
+    ws = _ws(ws, need)
+    shape = (geom.n_scan, grid.ny, grid.nx)
+    if out is None:
+        out = torch.empty(geom.echo_shape, dtype=torch.complex64, device=image.device)
+    _check(lib().adjoint_hybrid(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
+                                _dev_c64(image, shape, "image"), _dev_c64(out, geom.echo_shape, "out"),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
 
 
 STAGES = ("plan_tables", "scan_fft", "range_compress", "backproject", "kz_ifft")

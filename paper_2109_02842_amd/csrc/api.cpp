@@ -226,6 +226,30 @@ int reconstruct_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl
     return reconstruct_hybrid_events(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream);
 }
 
+int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* image,
+                   float* echo, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!image || !echo) return fail(PL_EINVAL, "adjoint_hybrid: null image or echo");
+    HybridPlan p;
+    DeviceTables dt;
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "adjoint_hybrid");
+    if (rc) return rc;
+    if (p.precision != PL_PREC_FP32 || !p.bp_gather)
+        return fail(PL_EUNSUPPORTED, "adjoint_hybrid: needs the FP32 plan with the pixel-per-lane back-projection");
+    char* w = static_cast<char*>(ws);
+    float2* St = reinterpret_cast<float2*>(w + p.off_spec);
+    float2* qt = reinterpret_cast<float2*>(w + p.off_q);
+    float2* Gt = reinterpret_cast<float2*>(w + p.off_G);
+    const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
+    if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
+    if ((rc = launch_kz_fft_adjoint(p, reinterpret_cast<const float2*>(image), Gt, tw_scan, stream))) return rc;
+    if ((rc = launch_fill_zero(qt, static_cast<size_t>(p.n_ch) * p.n_z * p.n_l, stream))) return rc;
+    if ((rc = launch_backproject_adjoint(p, dt, Gt, w, qt, stream))) return rc;
+    if ((rc = launch_range_adjoint(p, qt, w, St, stream))) return rc;
+    return launch_scan_fft_adjoint(g, St, reinterpret_cast<float2*>(echo), tw_scan, p.scan_rad, stream);
+}
+
 int bp_workspace_bytes(const pl_geometry* g, size_t* bytes) {
     pl::clear_error();
     if (!g || !bytes) return pl::fail(PL_EINVAL, "bp_workspace_bytes: null pointer");

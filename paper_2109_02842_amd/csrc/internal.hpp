@@ -133,6 +133,14 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
                             char* ws, float2* G, hipStream_t s);
 int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw,
                    hipStream_t s);
+// Adjoint steps (image -> echo), in the order they run.
+int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const float2* tw, hipStream_t s);
+int launch_fill_zero(float2* x, size_t n, hipStream_t s);
+int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, const float2* Gt, char* ws, float2* qt,
+                               hipStream_t s);
+int launch_range_adjoint(const HybridPlan& p, const float2* qt, char* ws, float2* St, hipStream_t s);
+int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const float2* tw,
+                            const Radices& rad, hipStream_t s);
 int launch_simulate(const pl_geometry* g, const DeviceTables& dt, int n_scat, const double* xyz,
                     const double* refl, float2* echo, hipStream_t s);
 int launch_bp(const pl_geometry* g, const DeviceTables& dt, const pl_image_grid* grid, int iz0,

@@ -472,6 +472,139 @@ __global__ void reset_counters_kernel(unsigned* c) {
     if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
+// Adjoint of the pixel-per-lane back-projection (the scatter form of A4):
+//   q~[c][kz][i] = sum_p sum_j [i = first tap(p, c) + j] w_j(p, c)
+//                  conj(exp(j k_ref l_c(p))) G~[p][kz],
+// the exact transpose of the forward interpolation.  One workgroup = one 8x8
+// tile x KB k_z bins with the same window starts, weights and LDS weight
+// slots as the forward kernel; per channel each lane (pixel) adds its four
+// taps times its rows of G~ into an LDS window (LDS float atomics), and the
+// window is then added to q~ with coalesced global float atomics (q~ must be
+// zero beforehand).  Sums of floats in a run-dependent order: results agree
+// between runs to rounding, not bitwise.
+template <int KB, int RSC>
+__global__ __launch_bounds__(64 * kGatherWaves) void backproject_adjoint_kernel(const float2* __restrict__ Gt,
+                                                                                const double* __restrict__ chan,
+                                                                                const double* __restrict__ llo,
+                                                                                BpgArgs a, float* __restrict__ qt) {
+    constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
+    constexpr int WS = 2 * RSC;  // window samples per LDS row
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    int* win = reinterpret_cast<int*>(smem);
+    float4* wts = reinterpret_cast<float4*>(smem + a.win_bytes);                        // [2][NB][2][64]
+    float* acc = reinterpret_cast<float*>(smem + a.win_bytes + 2 * NB * 2 * 64 * 16);  // [KB][WS][2]
+
+    const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
+    const int blk = work / a.n_tiles;
+    const int tile = work - blk * a.n_tiles;
+    const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpl = 2 * a.nchk;
+    const double kref_rev = a.kref[blk] * (0.5 / kPi);
+
+    {
+        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
+        for (int c = tid; c < a.n_ch; c += 64 * NW) {
+            const double* ch = chan + 4 * c;
+            const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
+                             sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
+            int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
+            s = max(0, min(s, a.n_l - wpl));
+            win[c] = s & ~1;
+        }
+    }
+    for (int e = tid; e < KB * WS * 2; e += 64 * NW) acc[e] = 0.f;
+
+    const int px = tx0 + (lane & 7), py = ty0 + (lane >> 3);
+    const bool pvalid = px < a.nx && py < a.ny;
+    const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
+    float2 v[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int kz = blk * KB + wave * RW + r;
+        v[r] = (pvalid && kz < a.n_z) ? Gt[(static_cast<size_t>(py) * a.nx + px) * a.n_z + kz] : make_float2(0.f, 0.f);
+    }
+
+    // four tap weights, carrier and first tap of (this lane's pixel, channel c)
+    auto weights = [&](int c, int par) {
+        float4 wa = make_float4(0.f, 0.f, 0.f, 0.f), wb = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < a.n_ch && pvalid) {
+            const double* ch = chan + 4 * c;
+            const double l = sqrt((xg - ch[0]) * (xg - ch[0]) + (yg - ch[1]) * (yg - ch[1])) +
+                             sqrt((xg - ch[2]) * (xg - ch[2]) + (yg - ch[3]) * (yg - ch[3]));
+            const double u = (l - llo[c]) * a.inv_du;
+            const double fl = floor(u);
+            const float t = static_cast<float>(u - fl);
+            const int i0 = max(0, min(static_cast<int>(fl) - 1 - win[c], wpl - 6));
+            wa.x = ((a.coef[0][3] * t + a.coef[0][2]) * t + a.coef[0][1]) * t + a.coef[0][0];
+            wa.y = ((a.coef[1][3] * t + a.coef[1][2]) * t + a.coef[1][1]) * t + a.coef[1][0];
+            wa.z = ((a.coef[2][3] * t + a.coef[2][2]) * t + a.coef[2][1]) * t + a.coef[2][0];
+            wa.w = ((a.coef[3][3] * t + a.coef[3][2]) * t + a.coef[3][1]) * t + a.coef[3][0];
+            const float2 car = cis_rev(kref_rev * l);
+            wb = make_float4(car.x, car.y, __int_as_float(i0), 0.f);
+        }
+        float4* slot = wts + (par * NB + wave) * 2 * 64 + lane;
+        slot[0] = wa;
+        slot[64] = wb;
+    };
+
+    __syncthreads();  // window starts visible, window zeroed
+    weights(wave, 0);
+    __syncthreads();
+#pragma unroll 1
+    for (int c0 = 0, par = 0; c0 < a.n_ch; c0 += NB, par ^= 1) {
+#pragma unroll 1
+        for (int cc = 0; cc < NB; ++cc) {
+            const int c = c0 + cc;
+            if (c >= a.n_ch) break;
+            if (cc == 0 && c0 + NB < a.n_ch) weights(c0 + NB + wave, par ^ 1);
+            const float4* slot = wts + (par * NB + cc) * 2 * 64 + lane;
+            const float4 wa = slot[0], wb = slot[64];
+            const int i0 = __float_as_int(wb.z);
+            const float w[4] = {wa.x, wa.y, wa.z, wa.w};
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                // conj(carrier) * G~
+                const float ur = wb.x * v[r].x + wb.y * v[r].y, ui = wb.x * v[r].y - wb.y * v[r].x;
+                float* row = acc + ((wave * RW + r) * WS + i0) * 2;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    atomicAdd(row + 2 * j, w[j] * ur);
+                    atomicAdd(row + 2 * j + 1, w[j] * ui);
+                }
+            }
+            __syncthreads();
+            // window -> q~[c][kz][s0 + i], rows past the last k_z bin skipped
+            const int s0 = win[c];
+            float* dst = qt + (static_cast<size_t>(c) * a.n_z * a.n_l + s0) * 2;
+            for (int e = tid; e < KB * wpl * 2; e += 64 * NW) {
+                const int row = e / (2 * wpl), k = e - row * 2 * wpl;
+                const int kz = blk * KB + row;
+                float* cell = acc + row * WS * 2 + k;
+                const float val = *cell;
+                if (kz < a.n_z && val != 0.f) atomicAdd(dst + static_cast<size_t>(kz) * a.n_l * 2 + k, val);
+                *cell = 0.f;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int KB, int RSC>
+int launch_adjoint_cfg(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* Gt,
+                       const double* chan, const double* llo, float* qt) {
+    auto fn = backproject_adjoint_kernel<KB, RSC>;
+    if (smem > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+        if (e != hipSuccess) return fail(PL_EDEVICE, "adjoint back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kGatherWaves), smem, s, Gt, chan, llo, a, qt);
+    return check_launch("adjoint back-projection");
+}
+
 template <int KB, int RSC>
 int launch_gather(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
                   const double* chan, const double* llo, float2* G) {
@@ -602,6 +735,25 @@ int launch_gather_batch(const void* descs, const void* items, const int* bounds,
     PL_GB(32, 12) PL_GB(32, 16) PL_GB(32, 20) PL_GB(32, 24) PL_GB(32, 33)
 #undef PL_GB
     return fail(PL_EUNSUPPORTED, "no batched back-projection for %d k_z bins, %d-chunk rows", kb, rsc);
+}
+
+int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, const float2* Gt, char* ws, float2* qt,
+                               hipStream_t s) {
+    int rc = check_gather_plan(p, p.window_pad);
+    if (rc) return rc;
+    const BpgArgs a = gather_args(p);
+    const size_t smem = static_cast<size_t>(a.win_bytes) + 2ull * kGatherBatch * 2 * 64 * 16 +
+                        2ull * p.block * p.window_pad * 2 * sizeof(float);
+    if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "adjoint back-projection needs %zu bytes of LDS", smem);
+    const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
+    const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
+    float* q = reinterpret_cast<float*>(qt);
+#define PL_GA(KB, RSC) \
+    if (p.block == KB && p.window_pad == RSC) return launch_adjoint_cfg<KB, RSC>(a, smem, blocks, s, Gt, dt.chan, llo, q);
+    PL_GA(64, 12) PL_GA(64, 16) PL_GA(64, 20) PL_GA(64, 24) PL_GA(64, 33)
+    PL_GA(32, 12) PL_GA(32, 16) PL_GA(32, 20) PL_GA(32, 24) PL_GA(32, 33)
+#undef PL_GA
+    return fail(PL_EUNSUPPORTED, "no adjoint back-projection for %d-chunk rows", p.window_pad);
 }
 
 size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks) {

@@ -225,4 +225,21 @@ int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const fl
                    "kz ifft");
 }
 
+// g[z][p] -> G~[p][kz]: adjoint of launch_kz_ifft (forward transform over z
+// with 1/n_z).
+int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const float2* tw, hipStream_t s) {
+    const long long npix = static_cast<long long>(p.nx) * p.ny;
+    return run_fft(image, Gt, tw, p.n_z, npix, 1, 1, 0, npix, p.n_z, 0, 1, -1, 1.0f / p.n_z, p.scan_rad, s,
+                   "kz fft (adjoint)");
+}
+
+// S~[c][kz][f] -> s~[c][m][f]: adjoint of launch_scan_fft (unnormalised
+// inverse transform over kz).
+int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const float2* tw,
+                            const Radices& rad, hipStream_t s) {
+    const long long nf = g->n_freq, nz = g->n_scan;
+    return run_fft(St, echo, tw, g->n_scan, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf,
+                   nz * nf, 1, nf, +1, 1.0f, rad, s, "scan fft (adjoint)");
+}
+
 }  // namespace pl

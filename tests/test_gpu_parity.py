@@ -513,3 +513,87 @@ def test_autotune_picks_a_valid_configuration(tmp_path):
     img = host(pr.reconstruct_hybrid(g, grid, dev(s), **best))
     assert rel(img, ohyb.image(ogeom.build(wl.array), grid, s)) < 1e-3
     assert at.autotune(g, grid, "bf16", cache=cache) == (best, times)     # cached
+
+
+# --------------------------------------------------- adjoint and autograd
+def _adjoint_case(name):
+    if name == "C1":
+        return W.C1.array, _fine_grid(45, 29, 0.003)
+    return multi_small().array, _fine_grid(27, 35, 0.004)
+
+
+@pytest.mark.parametrize("case", ["C1", "multi-small"])
+def test_adjoint_matches_oracle_and_dot_product(case):
+    desc, grid = _adjoint_case(case)
+    g = pr.make_geometry(desc)
+    assert pr.hybrid_plan_info(g, grid).bp_kernel == "pixel-lanes"
+    arr = ogeom.build(desc)
+    rng = np.random.default_rng(7)
+    img = W.complex_normal(rng, (desc.n_scan, grid.ny, grid.nx)).astype(np.complex64)
+    s = W.random_echo(desc, 8)
+    adj = host(pr.adjoint_hybrid(g, grid, dev(img)))
+    ref = ohyb.image_adjoint(arr, grid, img)
+    err = rel(adj, ref)
+    fwd = host(pr.reconstruct_hybrid(g, grid, dev(s)))
+    lhs = np.vdot(fwd.astype(np.complex128), img.astype(np.complex128))
+    rhs = np.vdot(s.astype(np.complex128), adj.astype(np.complex128))
+    dot = abs(lhs - rhs) / (np.linalg.norm(fwd) * np.linalg.norm(img))
+    say("adjoint", case, "rel L2 vs oracle", err, "dot-product mismatch", dot)
+    assert err < 1e-4
+    assert dot < 2e-6
+
+
+def test_autograd_gradients_against_oracle_and_finite_differences():
+    from paper_2109_02842_amd import autograd as ag
+    desc, grid = _adjoint_case("C1")
+    g = pr.make_geometry(desc)
+    arr = ogeom.build(desc)
+    rng = np.random.default_rng(11)
+    x = W.complex_normal(rng, (desc.n_scan, grid.ny, grid.nx)).astype(np.complex64)
+    s = W.random_echo(desc, 12)
+    xt = dev(x).requires_grad_(True)
+    res = ag.echo_model(g, grid, xt) - dev(s)
+    loss = torch.sum(res.real ** 2 + res.imag ** 2)
+    loss.backward()
+    grad = host(xt.grad)
+    # the oracle's gradient of ||H^H x - s||^2: 2 H (H^H x - s)
+    want = 2.0 * ohyb.image(arr, grid, ohyb.image_adjoint(arr, grid, x) - s)
+    err = rel(grad, want)
+    # central differences (the loss is quadratic: exact up to rounding)
+    d = W.complex_normal(np.random.default_rng(13), x.shape).astype(np.complex64)
+    eps = 1e-2 * np.linalg.norm(x) / np.linalg.norm(d)
+
+    def loss_at(v):
+        r = host(pr.adjoint_hybrid(g, grid, dev(v.astype(np.complex64)))).astype(np.complex128) - s
+        return float(np.vdot(r, r).real)
+
+    fd = (loss_at(x + eps * d) - loss_at(x - eps * d)) / (2 * eps)
+    dd = float(np.vdot(grad.astype(np.complex128), d.astype(np.complex128)).real)
+    say("autograd: grad vs oracle", err, "directional derivative", dd, "finite difference", fd)
+    assert err < 1e-4
+    assert abs(dd - fd) < 1e-4 * abs(fd)
+    # the imaging operator's own backward is the adjoint
+    st = dev(s).requires_grad_(True)
+    out = ag.reconstruct(g, grid, st)
+    (out.real.sum() + 2.0 * out.imag.sum()).backward()
+    ones = np.ones(out.shape, dtype=np.complex128) * (1.0 + 2.0j)
+    assert rel(host(st.grad), ohyb.image_adjoint(arr, grid, ones)) < 1e-4
+
+
+@pytest.mark.parametrize("method", ["cg", "sd"])
+def test_least_squares_refinement(method):
+    from paper_2109_02842_amd import autograd as ag
+    desc, grid = _adjoint_case("C1")
+    g = pr.make_geometry(desc)
+    # echo of a sparse scene through the echo model, plus 1 % noise
+    rng = np.random.default_rng(21)
+    truth = np.zeros((desc.n_scan, grid.ny, grid.nx), dtype=np.complex64)
+    idx = rng.choice(truth.size, 12, replace=False)
+    truth.reshape(-1)[idx] = W.complex_normal(rng, 12)
+    s = host(pr.adjoint_hybrid(g, grid, dev(truth)))
+    s = (s + 0.01 * np.linalg.norm(s) / np.sqrt(s.size) * W.complex_normal(rng, s.shape)).astype(np.complex64)
+    x, hist = ag.refine(g, grid, dev(s), steps=10, method=method)
+    say("refine", method, ["%.4g" % h for h in hist])
+    assert len(hist) == 11
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(hist, hist[1:]))
+    assert hist[-1] < 0.5 * hist[0]

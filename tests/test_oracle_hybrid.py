@@ -269,3 +269,43 @@ def test_multistatic_image_matches_bp_shape():
     a, b = gh / gh.max(), gb / gb.max()
     focal = (a > 0.1) | (b > 0.1)
     assert np.corrcoef(a[focal], b[focal])[0, 1] > 0.95
+
+
+def test_image_adjoint_dot_product():
+    # <H s, g> = <s, H^H g> for random echo and image (inner products in the
+    # complex128 sense, conjugate on the first argument)
+    wl = W.tiny("multi")
+    arr = geometry.build(wl.array)
+    rng = np.random.default_rng(5)
+    s = W.complex_normal(rng, arr_echo_shape(arr))
+    g = W.complex_normal(rng, (arr.z_scan.size, wl.grid.ny, wl.grid.nx))
+    lhs = np.vdot(hybrid.image(arr, wl.grid, s), g)
+    rhs = np.vdot(s, hybrid.image_adjoint(arr, wl.grid, g))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_image_adjoint_is_the_conjugate_transpose():
+    # brute force on a tiny problem: the matrix of the adjoint, built column
+    # by column from unit images, equals the conjugate transpose of the
+    # matrix of the forward operator built from unit echoes
+    desc = W.ArrayDesc(mode="mono", n_chords=2, radius=0.5, n_elem=2, spacing=W._D_MONO, n_scan=4,
+                       scan_step=0.005, n_freq=3, f_start=26e9, f_stop=34e9)
+    grid = W.ImageGrid(nx=2, ny=2, x0=-0.01, y0=0.02, dx=0.015, dy=0.01)
+    arr = geometry.build(desc)
+    es = arr_echo_shape(arr)
+    ne, ni = int(np.prod(es)), 4 * 2 * 2
+    M = np.zeros((ni, ne), dtype=np.complex128)
+    for j in range(ne):
+        e = np.zeros(ne, dtype=np.complex128)
+        e[j] = 1.0
+        M[:, j] = hybrid.image(arr, grid, e.reshape(es)).ravel()
+    A = np.zeros((ne, ni), dtype=np.complex128)
+    for j in range(ni):
+        e = np.zeros(ni, dtype=np.complex128)
+        e[j] = 1.0
+        A[:, j] = hybrid.image_adjoint(arr, grid, e.reshape(4, 2, 2)).ravel()
+    assert np.allclose(A, M.conj().T, rtol=0, atol=1e-12 * np.abs(M).max())
+
+
+def arr_echo_shape(arr):
+    return (arr.tx.shape[0], arr.z_scan.size, arr.k.size)
