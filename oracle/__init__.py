@@ -16,9 +16,11 @@ equations state:
   bp        -- brute-force back-projection, the paper's comparison method.
   nudft     -- the direct nonuniform DFT that the NUFFT of eq. (8a)
                approximates, for step-level checks.
+  omegak    -- the variant without NUFFT: the range transform by resampling
+               onto a uniform wavenumber grid and an inverse FFT.
 
 Every function is pinned by tests under ``tests/`` against facts that do not
 come from the oracle itself (closed forms, symmetries, brute force, focusing
 at known target positions, the paper's resolution formulas).
 """
-from . import geometry, simulate, hybrid, bp, nudft  # noqa: F401
+from . import geometry, simulate, hybrid, bp, nudft, omegak  # noqa: F401
