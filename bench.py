@@ -122,6 +122,8 @@ def main() -> int:
                     help="1: back-projection on the matrix cores (BF16/FP16 modes)")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--kz-block", type=int, default=0)
+    ap.add_argument("--range-method", default="nufft", choices=["nufft", "resample"],
+                    help="range compression: NUFFT (the paper's method) or uniform-grid resampling + IFFT")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -160,7 +162,8 @@ def main() -> int:
     torch.cuda.synchronize()
     opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
                 l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves,
-                mfma_backprojection=args.mfma_bp, tile_y=args.tile_y, kz_block=args.kz_block)
+                mfma_backprojection=args.mfma_bp, tile_y=args.tile_y, kz_block=args.kz_block,
+                range_method=args.range_method)
     plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
     img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
     log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
@@ -196,10 +199,12 @@ def main() -> int:
         return ms, stage, first_ms, float(np.median(steps_ms)), plan
 
     def parity(opts):
-        """Relative L2 error against the FP64 oracle on sampled (k_z, pixel)
-        pairs of the spectrum, for a seeded CN(0,1) echo of this workload."""
+        """Relative L2 error against the FP64 oracle of the same method on
+        sampled (k_z, pixel) pairs of the spectrum, for a seeded CN(0,1) echo
+        of this workload."""
         from oracle import geometry as ogeom
         from oracle import hybrid as ohyb
+        from oracle import omegak as oomk
         s = W.random_echo(a, 4242)
         out = pr.reconstruct_hybrid(geom, wl.grid, torch.from_numpy(s).cuda(), **opts)
         npix = wl.grid.nx * wl.grid.ny
@@ -209,7 +214,12 @@ def main() -> int:
         got = np.fft.fft(cols.astype(np.complex128), axis=0)[kap]
         arr = ogeom.build(a)
         px, py = ohyb.pixel_grid(wl.grid)
-        ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
+        if opts.get("range_method", "nufft") == "resample":
+            dkl = pr.hybrid_plan_info(geom, wl.grid, **opts).dk_uniform
+            ref = oomk.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix], dkl,
+                                   oomk.reference_lengths(arr, wl.grid))
+        else:
+            ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
         return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), f"{len(kap)} k_z x {pix.size} pixels"
 
     ms, stage, first_ms, med_ms, plan = time_path(opts, args.steps, args.warmup)
@@ -235,7 +245,8 @@ def main() -> int:
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {describe(wl)}", "path": f"hybrid-NUFFT {args.precision}",
+        "config": {"workload": f"{args.config}: {describe(wl)}",
+                   "path": f"hybrid-{'NUFFT' if args.range_method == 'nufft' else 'resample'} {args.precision}",
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
                    "tile": list(plan.tile), "kz_block": plan.block},
         "roofline": dict(roof, unit="TFLOP/s",
@@ -250,11 +261,12 @@ def main() -> int:
         log(f"[bench] {args.precision}: rel L2 vs oracle {err:.2e} ({sample})")
     if not args.no_variants:
         out["variants"] = {}
-        for name, prec, mbp in (("bf16", "bf16", 0), ("fp16", "fp16", 0), ("fp32", "fp32", 0),
-                                ("bf16-mfma-bp", "bf16", 1), ("fp16-mfma-bp", "fp16", 1)):
-            if prec == args.precision and mbp == args.mfma_bp:
+        for name, prec, mbp, rm in (("bf16", "bf16", 0, "nufft"), ("fp16", "fp16", 0, "nufft"),
+                                    ("fp32", "fp32", 0, "nufft"), ("bf16-mfma-bp", "bf16", 1, "nufft"),
+                                    ("fp16-mfma-bp", "fp16", 1, "nufft"), ("fp32-resample", "fp32", 0, "resample")):
+            if prec == args.precision and mbp == args.mfma_bp and rm == args.range_method:
                 continue
-            vopts = dict(opts, precision=prec, mfma_backprojection=mbp)
+            vopts = dict(opts, precision=prec, mfma_backprojection=mbp, range_method=rm)
             if mbp:
                 vopts.update(tile=0, tile_y=0, kz_block=0, kz_per_lane=0, waves=0)
             vms, vstage, _, vmed, _ = time_path(vopts, args.steps, 1)
@@ -286,6 +298,18 @@ def main() -> int:
                      "hybrid_speedup": value / bp_vps}
         log(f"[bench] BP: {nz} planes in {bms:.1f} ms -> {bp_vps:.3e} voxels/s; hybrid speedup "
             f"{value / bp_vps:.0f}x")
+        # the three methods of the paper's Table 2 on this workload (FP32)
+        times = {}
+        if args.precision == "fp32" and args.mfma_bp <= 0:
+            times[args.range_method] = ms
+        for name, rm in (("fp32", "nufft"), ("fp32-resample", "resample")):
+            if name in out.get("variants", {}):
+                times[rm] = out["variants"][name]["ms_per_step"]
+        if "nufft" in times and "resample" in times:
+            out["table2_analogue"] = {
+                "omegaK_NUFFT_BP_ms": times["nufft"], "omegaK_BP_ms": times["resample"],
+                "BP_ms": voxels / bp_vps * 1e3,
+                "note": "whole volume, FP32; BP extrapolated from the timed slab"}
 
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")

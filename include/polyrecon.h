@@ -174,6 +174,11 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
 #define PL_INTERP_LAGRANGE4 1 /* cubic Lagrange on the range samples             */
 #define PL_INTERP_LINEAR 2    /* linear (the simplest "1-D interpolation")       */
 
+/* Range compression (eq. 8a / 19a) methods. */
+#define PL_RANGE_NUFFT 0    /* type-1 NUFFT (the paper's method, default)         */
+#define PL_RANGE_RESAMPLE 1 /* resampling onto a uniform k grid + inverse FFT     */
+                            /* (the variant without NUFFT of Table 2), FP32 only  */
+
 /* Back-projection kernels (hybrid plan info). */
 #define PL_BP_KZ_LANES 0     /* VALU, one k_z bin per lane, weights broadcast */
 #define PL_BP_PIXEL_LANES 1  /* VALU, one pixel per lane, weights shared via LDS */
@@ -215,6 +220,21 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 16x8 and 16x16 allowed).
  * tile, tile_y, kz_per_lane, kz_block and waves are tuning knobs; results
  * agree to the method's tolerance whatever their values.
+ *   range_method  PL_RANGE_NUFFT (default) or PL_RANGE_RESAMPLE, the
+ *                 conventional evaluation the NUFFT replaces (Sec. I; Sec. II-A
+ *                 after eq. 8; "without NUFFT" in Table 2): per channel and
+ *                 k_z, the spectrum is demodulated by exp(+j k_L L_ref) (L_ref
+ *                 the path length rho_T + rho_R from the channel to the centre
+ *                 of the image grid, k_L = sqrt(k^2 - k_z^2/4)), interpolated
+ *                 by a centred 4-point Lagrange stencil over the frequency
+ *                 index at the k of every point k_L = m dkl of a uniform grid
+ *                 inside the propagating band, remodulated, weighted by
+ *                 k_L dkl / dk (k dk = k_L dk_L), and inverse-FFT'd onto the
+ *                 range grid.  dkl = 2 pi / (n_fine du) (plan info dk_uniform),
+ *                 so the profile is periodic in L with period n_fine du.
+ *                 FP32 precision only (PL_EUNSUPPORTED otherwise), at least two
+ *                 frequencies.  Its accuracy is that of the interpolation, not
+ *                 the NUFFT tolerance.
  */
 typedef struct pl_hybrid_opts {
     int32_t precision;
@@ -227,6 +247,7 @@ typedef struct pl_hybrid_opts {
     int32_t mfma_backprojection;
     int32_t tile_y;
     int32_t kz_block;
+    int32_t range_method;
 } pl_hybrid_opts;
 
 /* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */
@@ -245,6 +266,8 @@ typedef struct pl_hybrid_plan_info {
     double du;           /* range-grid step (m of rho_T + rho_R)                 */
     double beta;         /* exponential-of-semicircle kernel shape               */
     size_t workspace_bytes;
+    int32_t range_method;/* PL_RANGE_NUFFT or PL_RANGE_RESAMPLE                  */
+    double dk_uniform;   /* PL_RANGE_RESAMPLE: step of the uniform k_L grid, 2 pi / (n_fine du); else 0 */
 } pl_hybrid_plan_info;
 
 /*
@@ -265,7 +288,9 @@ int hybrid_workspace_bytes(const pl_geometry* geom, const pl_image_grid* grid,
  * The hybrid reconstruction of Sec. II (eqs. 2-9; multistatic 12-19):
  *   1. S = FFT over the scan axis of s (eq. 2/12);
  *   2. per channel and k_z, range compression q(l) = sum_f k_f S e^{j k'_f l}
- *      on a uniform range grid by a type-1 NUFFT (eq. 8a/19a);
+ *      on a uniform range grid by a type-1 NUFFT (eq. 8a/19a), or with
+ *      range_method PL_RANGE_RESAMPLE by uniform-grid resampling and an
+ *      inverse FFT;
  *   3. per k_z, interpolation of q at each pixel's range l_c(p) = rho
  *      (mono) or rho_T + rho_R (multi), carrier e^{j k_ref l}, and the sum
  *      over channels (eq. 8b/19b);
@@ -307,7 +332,8 @@ int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid
  * the direct type-2 sum over the range grid (eq. 8a/19a transposed) and the
  * unnormalised inverse transform over k_z.  It serves as the echo model of
  * least-squares refinement (scene image -> echo).  FP32 plans with the
- * pixel-per-lane back-projection only (PL_EUNSUPPORTED otherwise); the same
+ * pixel-per-lane back-projection and the NUFFT range method only
+ * (PL_EUNSUPPORTED otherwise); the same
  * workspace size as reconstruct_hybrid.  The back-projection adjoint adds
  * with float atomics, so results agree between runs to rounding, not bitwise.
  * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.

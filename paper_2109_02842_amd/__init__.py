@@ -26,6 +26,7 @@ PL_MONO, PL_MULTI = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 INTERPS = {"bspline4": 0, "lagrange4": 1, "linear": 2}
 BP_KERNELS = {0: "kz-lanes", 1: "pixel-lanes", 2: "mfma"}
+RANGE_METHODS = {"nufft": 0, "resample": 1}
 WARN_ELEMENT_SPACING, WARN_SCAN_STEP = 1, 2
 
 _ERRNAMES = {PL_EINVAL: "PL_EINVAL", PL_EGEOM: "PL_EGEOM", PL_EDEVICE: "PL_EDEVICE",
@@ -60,7 +61,7 @@ class HybridOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("interp", C.c_int32), ("l_oversample", C.c_double),
                 ("nufft_tol", C.c_double), ("tile", C.c_int32), ("kz_per_lane", C.c_int32),
                 ("waves", C.c_int32), ("mfma_backprojection", C.c_int32), ("tile_y", C.c_int32),
-                ("kz_block", C.c_int32)]
+                ("kz_block", C.c_int32), ("range_method", C.c_int32)]
 
 
 class HybridPlanInfo(C.Structure):
@@ -68,7 +69,7 @@ class HybridPlanInfo(C.Structure):
                 ("kernel_width", C.c_int32), ("n_blocks", C.c_int32), ("block", C.c_int32),
                 ("window", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("bp_kernel", C.c_int32), ("waves", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t), ("range_method", C.c_int32), ("dk_uniform", C.c_double)]
 
 
 _P = C.c_void_p
@@ -211,14 +212,16 @@ def _grid(grid) -> ImageGridC:
 
 
 def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
-          waves=0, mfma_backprojection=0, tile_y=0, kz_block=0) -> HybridOpts:
+          waves=0, mfma_backprojection=0, tile_y=0, kz_block=0, range_method="nufft") -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {list(INTERPS)}")
+    if range_method not in RANGE_METHODS:
+        raise ValueError(f"range_method must be one of {list(RANGE_METHODS)}")
     return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol),
                       int(tile), int(kz_per_lane), int(waves), int(mfma_backprojection), int(tile_y),
-                      int(kz_block))
+                      int(kz_block), RANGE_METHODS[range_method])
 
 
 def check_sampling(geom: Geometry, grid) -> int:
@@ -243,6 +246,8 @@ class PlanInfo:
     k_ref: list
     bp_kernel: str = "kz-lanes"
     waves: int = 4
+    range_method: str = "nufft"
+    dk_uniform: float = 0.0         # resampling method: step of the uniform k_L grid (rad/m)
 
     @property
     def mfma_backprojection(self) -> bool:
@@ -257,7 +262,8 @@ def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
     return PlanInfo(info.n_kz, info.n_l, info.n_fine, info.kernel_width, info.n_blocks, info.block,
                     info.window, (info.tile_x, info.tile_y), info.du, info.beta,
                     int(info.workspace_bytes), list(kref[: info.n_blocks]), BP_KERNELS[info.bp_kernel],
-                    int(info.waves))
+                    int(info.waves), {v: k for k, v in RANGE_METHODS.items()}[info.range_method],
+                    float(info.dk_uniform))
 
 
 def hybrid_workspace_bytes(geom: Geometry, grid, **opts) -> int:

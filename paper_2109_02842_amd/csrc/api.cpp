@@ -85,6 +85,8 @@ int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     info->du = p.du;
     info->beta = p.beta;
     info->workspace_bytes = p.total;
+    info->range_method = p.range_method;
+    info->dk_uniform = p.range_method == PL_RANGE_RESAMPLE ? p.dkl : 0.0;
     if (k_ref_host) std::memcpy(k_ref_host, p.kref, sizeof(double) * p.n_blocks);
     return PL_OK;
 }
@@ -237,6 +239,8 @@ int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     if (rc) return rc;
     if (p.precision != PL_PREC_FP32 || !p.bp_gather)
         return fail(PL_EUNSUPPORTED, "adjoint_hybrid: needs the FP32 plan with the pixel-per-lane back-projection");
+    if (p.range_method != PL_RANGE_NUFFT)
+        return fail(PL_EUNSUPPORTED, "adjoint_hybrid: the adjoint is of the NUFFT range compression");
     char* w = static_cast<char*>(ws);
     float2* St = reinterpret_cast<float2*>(w + p.off_spec);
     float2* qt = reinterpret_cast<float2*>(w + p.off_q);

@@ -80,6 +80,8 @@ struct HybridPlan {
     int force_tile = 0, force_tile_y = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0, force_kb = 0;
     bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
     bool bp_gather = false;          // VALU back-projection with one pixel per lane
+    int range_method = PL_RANGE_NUFFT;
+    double dkl = 0, k0 = 0, dk = 0;  // resampling: uniform k_L step, frequency grid start and step
     double half_band = 0, sigma_used = 0;
     // range grid and NUFFT
     int n_l = 0, n_fine = 0, W = 0;
@@ -95,7 +97,7 @@ struct HybridPlan {
     // interpolation weights w_k(t) = sum_j coef[k][j] t^j, taps at floor(u)-1+k
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
-    size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_tw_scan = 0, off_tw_fine = 0;
+    size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_tw_scan = 0, off_tw_fine = 0;
     size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, total = 0;
 };
 
@@ -123,6 +125,8 @@ int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, cons
 int launch_twiddles(float2* tw, int n, hipStream_t s);
 int launch_range_compress_fp32(const HybridPlan& p, const float2* spec, char* ws, float2* q,
                                hipStream_t s);
+int launch_range_compress_resample(const HybridPlan& p, const float2* spec, char* ws, float2* q,
+                                   hipStream_t s);
 int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q,
                                hipStream_t s);
 int launch_range_compress_mfma_split(const HybridPlan& p, const float2* spec, char* ws,

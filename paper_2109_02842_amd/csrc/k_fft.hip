@@ -22,13 +22,15 @@ __device__ double dist_to_rect(double px, double py, double x0, double x1, doubl
 // Fills the per-call tables of the hybrid plan:
 //   llo[c]       start of channel c's range grid (lowest range over the pixel
 //                rectangle minus two steps)
+//   lref[c]      range rho_T + rho_R from channel c to the centre of the pixel
+//                rectangle (demodulation reference of the resampling method)
 //   tw_scan[t]   exp(-2 pi i t / n_z);  tw_fine[t]  exp(-2 pi i t / n_fine)
 //   deap[i]      1 / (h * FT of the spreading kernel) at output mode i - n_l/2
 //   kp[kz][f]    k' = k_rho - k_ref(block), k_rho = sqrt(k^2 - k_z^2/4) (0 if evanescent)
 //   wk[kz][f]    k_f (weight of "k dk") times the B-spline prefilter, 0 if evanescent
 __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ chan,
                                    const double* __restrict__ k, double* __restrict__ llo,
-                                   float2* __restrict__ tw_scan, float2* __restrict__ tw_fine,
+                                   double* __restrict__ lref, float2* __restrict__ tw_scan, float2* __restrict__ tw_fine,
                                    float* __restrict__ deap, double* __restrict__ kp,
                                    float* __restrict__ wk) {
     const long long n0 = a.n_ch, n1 = n0 + a.n_z, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
@@ -40,6 +42,8 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
             const double lmin = dist_to_rect(chan[4 * c], chan[4 * c + 1], a.gx0, a.gx1, a.gy0, a.gy1) +
                                 dist_to_rect(chan[4 * c + 2], chan[4 * c + 3], a.gx0, a.gx1, a.gy0, a.gy1);
             llo[c] = lmin - 2.0 * a.du;
+            const double cx = 0.5 * (a.gx0 + a.gx1), cy = 0.5 * (a.gy0 + a.gy1);
+            lref[c] = hypot(cx - chan[4 * c], cy - chan[4 * c + 1]) + hypot(cx - chan[4 * c + 2], cy - chan[4 * c + 3]);
         } else if (idx < n1) {
             const int t = static_cast<int>(idx - n0);
             double s, c;
@@ -199,7 +203,8 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
                             static_cast<long long>(p.n_z) * p.n_f;
     const int blocks = static_cast<int>(std::min<long long>((total + 255) / 256, 4096));
     hipLaunchKernelGGL(plan_tables_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan, dt.k,
-                       reinterpret_cast<double*>(ws + p.off_llo), reinterpret_cast<float2*>(ws + p.off_tw_scan),
+                       reinterpret_cast<double*>(ws + p.off_llo), reinterpret_cast<double*>(ws + p.off_lref),
+                       reinterpret_cast<float2*>(ws + p.off_tw_scan),
                        reinterpret_cast<float2*>(ws + p.off_tw_fine), reinterpret_cast<float*>(ws + p.off_deap),
                        reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk));
     return check_launch("plan tables");

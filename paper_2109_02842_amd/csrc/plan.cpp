@@ -73,6 +73,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.force_bp_mfma = opts->mfma_backprojection;
         p.force_tile_y = opts->tile_y;
         p.force_kb = opts->kz_block;
+        p.range_method = opts->range_method;
     }
     if (p.force_kpl != 0 && p.force_kpl != 1 && p.force_kpl != 2 && p.force_kpl != 4)
         return fail(PL_EINVAL, "kz_per_lane must be 0, 1, 2 or 4");
@@ -86,6 +87,13 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         return fail(PL_EINVAL, "kz_block must be 0, 32, 64 or 128");
     if (p.precision < PL_PREC_FP32 || p.precision > PL_PREC_FP16)
         return fail(PL_EINVAL, "unknown precision %d", p.precision);
+    if (p.range_method != PL_RANGE_NUFFT && p.range_method != PL_RANGE_RESAMPLE)
+        return fail(PL_EINVAL, "unknown range_method %d", p.range_method);
+    if (p.range_method == PL_RANGE_RESAMPLE) {
+        if (p.precision != PL_PREC_FP32)
+            return fail(PL_EUNSUPPORTED, "the resampling range compression runs in FP32 only");
+        if (p.n_f < 2) return fail(PL_EUNSUPPORTED, "the resampling range compression needs two frequencies");
+    }
     if (p.interp < PL_INTERP_BSPLINE4 || p.interp > PL_INTERP_LINEAR)
         return fail(PL_EINVAL, "unknown interpolation %d", p.interp);
     if (!(p.sigma_l >= 2.0 && p.sigma_l <= 64.0)) return fail(PL_EINVAL, "l_oversample must be in [2, 64]");
@@ -274,6 +282,21 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     if (p.n_fine > kMaxFine)
         return fail(PL_EUNSUPPORTED, "range grid of %d samples exceeds %d (lower l_oversample)", nl, kMaxFine / 2);
     factor_radices(p.n_fine, &p.fine_rad);
+    if (p.range_method == PL_RANGE_RESAMPLE) {
+        // uniform k_L grid whose inverse FFT lands on the range grid: step
+        // 2 pi / (n_fine du); a block's band of 2 half_band holds at most
+        // n_fine / sigma + 1 of its points, so they never share a bin
+        p.dkl = 2.0 * kPi / (p.n_fine * p.du);
+        p.k0 = g->k[0];
+        p.dk = (g->k[p.n_f - 1] - g->k[0]) / (p.n_f - 1);
+        if (!(p.dk > 0) || 2.0 * p.half_band / p.dkl + 2.0 > p.n_fine)
+            return fail(PL_EUNSUPPORTED, "resampling grid does not fit the range grid");
+        // reference wavenumbers on the grid (the reference cancels between
+        // eqs. 8a and 8b, any value is exact): the grid's k' are then whole
+        // multiples of dkl and land on FFT bins without a residual shift.  The
+        // band edges move by at most dkl / 2 = sigma half_band / n_fine.
+        for (int b = 0; b < p.n_blocks; ++b) p.kref[b] = p.dkl * std::nearbyint(p.kref[b] / p.dkl);
+    }
 
     // Exponential-of-semicircle kernel (Barnett, Magland, af Klinteberg 2019)
     // for a 2x oversampled fine grid: width W = ceil(log10(1/tol)) + 1,
@@ -312,6 +335,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_q = take(nch * nz * static_cast<size_t>(p.n_l) * 8);
     p.off_G = take(npix * nz * 8);
     p.off_llo = take(nch * 8);
+    p.off_lref = take(nch * 8);
     p.off_tw_scan = take(nz * 8);
     p.off_tw_fine = take(static_cast<size_t>(p.n_fine) * 8);
     p.off_deap = take(static_cast<size_t>(p.n_l) * 4);

@@ -219,6 +219,33 @@ def test_valu_backprojection_plan_rules():
     assert p1.bp_kernel == "kz-lanes" and p1.tile == (4, 4)
 
 
+def test_resample_range_method_plan_rules():
+    g = pr.make_geometry(W.C2.array)
+    base = pr.hybrid_plan_info(g, W.C2.grid)
+    assert base.range_method == "nufft" and base.dk_uniform == 0.0
+    p = pr.hybrid_plan_info(g, W.C2.grid, range_method="resample")
+    assert p.range_method == "resample"
+    # the inverse FFT of the uniform grid lands on the range grid
+    assert p.dk_uniform == pytest.approx(2 * math.pi / (p.n_fine * p.du), rel=1e-12)
+    # same range grid and back-projection as the NUFFT plan
+    assert (p.n_l, p.du, p.bp_kernel, p.block) == (base.n_l, base.du, base.bp_kernel, base.block)
+    # reference wavenumbers moved onto the grid (by at most half a step)
+    for kr, kb in zip(p.k_ref, base.k_ref):
+        assert abs(kr / p.dk_uniform - round(kr / p.dk_uniform)) < 1e-9
+        assert abs(kr - kb) <= 0.5 * p.dk_uniform + 1e-9
+    # a block's propagating band fits the transform: at most n_fine / 8 + 1 grid points
+    k = ogeom.build(W.C2.array).k
+    assert (k[-1] - k[0]) / p.dk_uniform + 1 <= p.n_fine
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, W.C2.grid, range_method="resample", precision="bf16")
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(pr.make_geometry(replace(W.C1.array, n_freq=1)), W.C1.grid, range_method="resample")
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(ValueError):
+        pr.hybrid_plan_info(g, W.C2.grid, range_method="stolt")
+
+
 def test_batch_argument_errors_before_device_use():
     import ctypes as C
     L = pr.lib()
