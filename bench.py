@@ -278,6 +278,30 @@ def main() -> int:
             log(f"[bench] {name}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
                 f"backproject {vstage['backproject']:.3f} ms; rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}")
 
+    if not args.no_variants:
+        # the adjoint (image -> echo) of the FP32 pixel-per-lane plan: one
+        # call per step, the same workspace size as the reconstruction
+        aopts = dict(opts, precision="fp32", mfma_backprojection=0, range_method="nufft")
+        aplan = pr.hybrid_plan_info(geom, wl.grid, **aopts)
+        if aplan.bp_kernel == "pixel-lanes":
+            aws = pr.workspace(aplan.workspace_bytes)
+            aout = torch.empty(geom.echo_shape, dtype=torch.complex64, device="cuda")
+            for _ in range(args.warmup + 1):
+                pr.adjoint_hybrid(geom, wl.grid, img, out=aout, ws=aws, **aopts)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                pr.adjoint_hybrid(geom, wl.grid, img, out=aout, ws=aws, **aopts)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ams = e0.elapsed_time(e1) / args.steps
+            out["adjoint"] = {"ms_per_call": ams, "voxels_per_s": voxels / (ams * 1e-3),
+                              "note": "image -> echo, FP32, NUFFT plan with the pixel-per-lane kernel"}
+            log(f"[bench] adjoint: {ams:.3f} ms per call")
+            del aws
+
     if not args.no_bp:
         nz = max(1, min(args.bp_planes, a.n_scan))
         iz0 = a.n_scan // 2 - nz // 2
