@@ -334,8 +334,9 @@ int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid
  * least-squares refinement (scene image -> echo).  FP32 plans with the
  * pixel-per-lane back-projection and the NUFFT range method only
  * (PL_EUNSUPPORTED otherwise); the same
- * workspace size as reconstruct_hybrid.  The back-projection adjoint adds
- * with float atomics, so results agree between runs to rounding, not bitwise.
+ * workspace size as reconstruct_hybrid.  Every element of the intermediate
+ * range profiles is summed by one workgroup in a fixed order (no atomics), so
+ * results are bitwise repeatable.
  * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.
  */
 int adjoint_hybrid(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,

@@ -248,8 +248,7 @@ int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
     if ((rc = launch_kz_fft_adjoint(p, reinterpret_cast<const float2*>(image), Gt, tw_scan, stream))) return rc;
-    if ((rc = launch_fill_zero(qt, static_cast<size_t>(p.n_ch) * p.n_z * p.n_l, stream))) return rc;
-    if ((rc = launch_backproject_adjoint(p, dt, Gt, w, qt, stream))) return rc;
+    if ((rc = launch_backproject_adjoint(p, dt, Gt, w, qt, stream))) return rc;  // writes every element of q~
     if ((rc = launch_range_adjoint(p, qt, w, St, stream))) return rc;
     return launch_scan_fft_adjoint(g, St, reinterpret_cast<float2*>(echo), tw_scan, p.scan_rad, stream);
 }

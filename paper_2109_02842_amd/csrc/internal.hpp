@@ -139,7 +139,6 @@ int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const fl
                    hipStream_t s);
 // Adjoint steps (image -> echo), in the order they run.
 int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const float2* tw, hipStream_t s);
-int launch_fill_zero(float2* x, size_t n, hipStream_t s);
 int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, const float2* Gt, char* ws, float2* qt,
                                hipStream_t s);
 int launch_range_adjoint(const HybridPlan& p, const float2* qt, char* ws, float2* St, hipStream_t s);

@@ -2,9 +2,10 @@
 //   S~[c][kz][f] = w[kz][f] sum_i q~[c][kz][i] exp(-j k'[kz][f] (l_lo[c] + i du)),
 // the transpose of q[c][kz][i] = sum_f w[kz][f] S[c][kz][f] exp(+j k' l_i),
 // which the forward path evaluates by NUFFT.  Here the sums are direct: one
-// wavefront per (c, kz), lanes over frequencies, the phasor advanced by a
+// wavefront per (c, kz), lanes over frequencies, the profile read 64 samples
+// per coalesced load and broadcast by readlane, the phasor advanced by a
 // recurrence in FP32 and re-anchored from an FP64-reduced phase every 32
-// samples.  And a fill kernel for buffers that are accumulated into.
+// samples.
 #include "device.hpp"
 
 namespace pl {
@@ -26,30 +27,29 @@ __global__ __launch_bounds__(256) void range_adjoint_kernel(const float2* __rest
     const int c = static_cast<int>(pair / a.n_z), kz = static_cast<int>(pair - static_cast<long long>(c) * a.n_z);
     const float2* row = qt + pair * a.n_l;
     const double l0 = llo[c];
-    for (int f = lane; f < a.n_f; f += 64) {
-        const double k = kp[static_cast<size_t>(kz) * a.n_f + f];
-        const float w = wk[static_cast<size_t>(kz) * a.n_f + f];
-        float2 acc = make_float2(0.f, 0.f);
-        if (w != 0.f) {
-            const double rev = -k * (0.5 / kPi);  // phase in revolutions per metre
-            const float2 d = cis_rev(rev * a.du);
-            float2 ph = make_float2(1.f, 0.f);
-            for (int i = 0; i < a.n_l; ++i) {
-                if ((i & 31) == 0) ph = cis_rev(rev * (l0 + i * a.du));
-                const float2 q = row[i];
-                acc.x += ph.x * q.x - ph.y * q.y;
-                acc.y += ph.x * q.y + ph.y * q.x;
+    for (int f0 = 0; f0 < a.n_f; f0 += 64) {
+        const int f = f0 + lane;
+        const bool fok = f < a.n_f;
+        const double k = fok ? kp[static_cast<size_t>(kz) * a.n_f + f] : 0.0;
+        const float w = fok ? wk[static_cast<size_t>(kz) * a.n_f + f] : 0.f;
+        const double rev = -k * (0.5 / kPi);  // phase in revolutions per metre
+        const float2 d = cis_rev(rev * a.du);
+        float2 acc = make_float2(0.f, 0.f), ph = make_float2(1.f, 0.f);
+        // 64 range samples per coalesced load, broadcast to the lanes by readlane
+        for (int ib = 0; ib < a.n_l; ib += 64) {
+            const float2 qv = ib + lane < a.n_l ? row[ib + lane] : make_float2(0.f, 0.f);
+            const int nb = min(64, a.n_l - ib);
+            for (int j = 0; j < nb; ++j) {
+                if ((j & 31) == 0) ph = cis_rev(rev * (l0 + (ib + j) * a.du));
+                const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.x), j));
+                const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qv.y), j));
+                acc.x += ph.x * qx - ph.y * qy;
+                acc.y += ph.x * qy + ph.y * qx;
                 ph = cmul(ph, d);
             }
         }
-        St[pair * a.n_f + f] = make_float2(w * acc.x, w * acc.y);
+        if (fok) St[pair * a.n_f + f] = make_float2(w * acc.x, w * acc.y);
     }
-}
-
-__global__ void fill_zero_kernel(float2* __restrict__ x, size_t n) {
-    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        x[i] = make_float2(0.f, 0.f);
 }
 
 }  // namespace
@@ -70,11 +70,5 @@ int launch_range_adjoint(const HybridPlan& p, const float2* qt, char* ws, float2
     return check_launch("range compression (adjoint)");
 }
 
-int launch_fill_zero(float2* x, size_t n, hipStream_t s) {
-    if (n == 0) return PL_OK;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, x, n);
-    return check_launch("fill");
-}
 
 }  // namespace pl

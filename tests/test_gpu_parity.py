@@ -545,6 +545,28 @@ def test_adjoint_matches_oracle_and_dot_product(case):
     say("adjoint", case, "rel L2 vs oracle", err, "dot-product mismatch", dot)
     assert err < 1e-4
     assert dot < 2e-6
+    # owner-computes adjoint: fixed summation order, bitwise repeatable
+    adj2 = host(pr.adjoint_hybrid(g, grid, dev(img)))
+    assert np.array_equal(adj.view(np.uint32), adj2.view(np.uint32))
+
+
+def test_adjoint_ragged_grid_and_64_bin_blocks():
+    # ragged tiles, both k_z block sizes of the pixel-per-lane plan, and
+    # segments that end inside the range grid
+    desc, _ = _adjoint_case("C1")
+    grid = _fine_grid(37, 21, 0.0031)
+    g = pr.make_geometry(desc)
+    arr = ogeom.build(desc)
+    rng = np.random.default_rng(9)
+    img = W.complex_normal(rng, (desc.n_scan, grid.ny, grid.nx)).astype(np.complex64)
+    ref = ohyb.image_adjoint(arr, grid, img)
+    for kb in (32, 64):
+        plan = pr.hybrid_plan_info(g, grid, kz_block=kb)
+        assert plan.bp_kernel == "pixel-lanes" and plan.block == kb
+        adj = host(pr.adjoint_hybrid(g, grid, dev(img), kz_block=kb))
+        err = rel(adj, ref)
+        say("adjoint ragged", kb, "k_z bins: rel L2", err, "n_l", plan.n_l)
+        assert err < 1e-4
 
 
 def test_autograd_gradients_against_oracle_and_finite_differences():
