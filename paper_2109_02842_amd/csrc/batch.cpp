@@ -104,9 +104,9 @@ int make_hybrid_batch(int32_t n, const pl_geometry* const* geoms, const pl_image
             DeviceTables dt;
             int rc = geoms[s]->device_tables(&dt);
             if (rc) return bail(rc);
-            rc = build_gather_batch_desc(p, dt.chan, b->ws_off[s], rsc, desc.data() + gather_batch_desc_bytes() * s);
+            rc = build_gather_batch_desc(p, b->ws_off[s], rsc, desc.data() + gather_batch_desc_bytes() * s);
             if (rc) return bail(rc);
-            q.smem = std::max(q.smem, backproject_gather_lds_bytes(p.n_ch, kb, rsc));
+            q.smem = std::max(q.smem, backproject_gather_lds_bytes(kb, rsc));
             const int n_tiles = p.tiles_x * p.tiles_y;
             for (int blk = 0; blk < p.n_blocks; ++blk)
                 for (int t = 0; t < n_tiles; ++t) {

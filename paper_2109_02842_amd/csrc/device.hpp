@@ -106,6 +106,14 @@ __device__ __forceinline__ void dft_small<5>(float2* a, int sgn) {
 // One Stockham stage of radix R over `ntr` transforms of length n stored at
 // src[t * ld + i]; writes dst.  tw[j] = exp(-2 pi i j / n).  Ns is the product
 // of the radices of the previous stages.
+// floor(x / d) for 0 <= x, 1 <= d and x + d < 2^22, from inv_d = 1.0f / d
+// (correctly rounded): (x + 1/2) / d = floor(x / d) + f with f in
+// [1/(2d), 1 - 1/(2d)], and the float product is within (x + d) 2^-23 / d of
+// it, less than 1/(2d).  A few instructions instead of an integer division.
+__device__ __forceinline__ int div_small(int x, float inv_d) {
+    return static_cast<int>((static_cast<float>(x) + 0.5f) * inv_d);
+}
+
 template <int R>
 __device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, float2* __restrict__ dst,
                                                int n, int ld, int ntr, int Ns,
@@ -114,10 +122,12 @@ __device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, f
     const int nb = n / R;
     const int tstep = n / (Ns * R);
     const int total = nb * ntr;
+    const float inv_nb = 1.0f / nb, inv_ns = 1.0f / Ns;
     for (int b = tid; b < total; b += nthreads) {
-        const int t = b / nb;
+        const int t = ntr == 1 ? 0 : div_small(b, inv_nb);
         const int j = b - t * nb;
-        const int k = j % Ns;
+        const int jq = div_small(j, inv_ns);
+        const int k = j - jq * Ns;
         const float2* s = src + t * ld;
         float2 a[R];
 #pragma unroll
@@ -129,7 +139,7 @@ __device__ __forceinline__ void stockham_stage(const float2* __restrict__ src, f
             a[r] = cmul(a[r], w);
         }
         dft_small<R>(a, sgn);
-        float2* d = dst + t * ld + (j / Ns) * Ns * R + k;
+        float2* d = dst + t * ld + jq * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) d[r * Ns] = a[r];
     }

@@ -98,12 +98,12 @@ struct HybridPlan {
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
     size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_tw_scan = 0, off_tw_fine = 0;
-    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, total = 0;
+    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0, total = 0;
 };
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 size_t backproject_mfma_lds_bytes(int n_ch, int kz_block);
-size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks);
+size_t backproject_gather_lds_bytes(int rows, int row_chunks);
 
 // Batched pixel-per-lane back-projection (one persistent launch for several
 // scans): a per-scan descriptor of gather_batch_desc_bytes() bytes, built on
@@ -111,7 +111,7 @@ size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks);
 // contiguous per-XCD queues delimited by bounds[0..8] (device ints); eight
 // counters (unsigned) live in the caller's workspace.
 size_t gather_batch_desc_bytes();
-int build_gather_batch_desc(const HybridPlan& p, const double* chan, size_t ws_off, int rsc, void* out);
+int build_gather_batch_desc(const HybridPlan& p, size_t ws_off, int rsc, void* out);
 int gather_batch_grid(int kb, int rsc, size_t smem, int* blocks);
 int launch_gather_batch(const void* descs, const void* items, const int* bounds, unsigned* counters, char* ws,
                         int kb, int rsc, size_t smem, int blocks, hipStream_t s);
@@ -120,6 +120,10 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
 
 // ---------------------------------------------------------- launchers
 int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
+// Per (tile, channel) geometry of the pixel-per-lane back-projection (after
+// the plan tables: reads l_lo); a no-op for plans without that kernel.
+size_t gather_table_bytes(const HybridPlan& p);
+int launch_gather_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
 int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const float2* tw,
                     const Radices& rad, hipStream_t s);
 int launch_twiddles(float2* tw, int n, hipStream_t s);

@@ -253,18 +253,34 @@ int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s
 // are copied into LDS by 16-byte direct global-to-LDS loads one channel
 // ahead, double-buffered.
 struct BpgArgs {
-    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nchk, win_bytes;
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nchk, mono;
     double x0, y0, dx, dy, inv_du, reach;
     float coef[4][4];
     double kref[kMaxBlocks];
 };
 
-// One scan of a batch: its arguments, channel table, and byte offsets of its
-// range profiles, range origins and spectrum in the batch workspace.
+// Per (8x8 tile, channel) geometry of the pixel-per-lane back-projection,
+// computed once per call in float64 (tile-major: entry tile * n_ch + c).  A
+// pixel's range follows from the tile centre's in float32 without loss:
+// with X the vector from an antenna to the centre, D = |X| and d the
+// pixel's offset, |X + d| - D = s / (D + sqrt(D^2 + s)), s = 2 X.d + d.d,
+// a difference of at most a tile diagonal, exact to float32 rounding.
+struct GatherTileEntry {
+    double lc;             // range rho_T + rho_R from the channel to the tile centre
+    int win;               // first staged sample of the tile's window (even)
+    int base;              // floor(u(centre)) - 1 - win
+    float uf;              // u(centre) - floor(u(centre)), u = (l - l_lo) / du
+    float xt, yt, dt;      // centre minus Tx position, and its length
+    float xr, yr, dr;      // centre minus Rx position, and its length
+    float pad_;
+};
+static_assert(sizeof(GatherTileEntry) == 48, "tile table entry");
+
+// One scan of a batch: its arguments and byte offsets of its range profiles,
+// tile table and spectrum in the batch workspace.
 struct BatchScanDesc {
     BpgArgs a;
-    const double* chan;
-    unsigned long long q_off, llo_off, g_off;
+    unsigned long long q_off, tab_off, g_off;
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -278,37 +294,26 @@ constexpr int kGatherBatch = 4;   // channels per weight batch
 
 // RSC 16-byte chunks per LDS row, of which nchk are staged: the window's
 // chunks and one more, since a pixel may read one chunk past its last tap.
-// One (k_z block, tile) work item; smem = the workgroup's LDS (win_bytes of
-// window starts, then the weight slots, then the two row buffers).
+// One (k_z block, tile) work item; tab = the scan's tile table; smem = the
+// workgroup's LDS (the weight slots, then the two row buffers).
 template <int KB, int RSC>
 __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __restrict__ q,
-                                            const double* __restrict__ chan, const double* __restrict__ llo,
-                                            float2* __restrict__ G, int blk, int tile, unsigned char* smem) {
+                                            const GatherTileEntry* __restrict__ tab, float2* __restrict__ G,
+                                            int blk, int tile, unsigned char* smem) {
     constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
     constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
     constexpr unsigned kBufBytes = KB * RSC * 16;
-    int* win = reinterpret_cast<int*>(smem);
-    float4* wts = reinterpret_cast<float4*>(smem + a.win_bytes);   // [2][NB][2][64]
-    const unsigned lds_q = static_cast<unsigned>(a.win_bytes + 2 * NB * 2 * 64 * 16);
+    float4* wts = reinterpret_cast<float4*>(smem);   // [2][NB][2][64]
+    constexpr unsigned lds_q = 2 * NB * 2 * 64 * 16;
 
     const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpl = 2 * a.nchk;
     const double kref_rev = a.kref[blk] * (0.5 / kPi);
-
-    // even window start of every channel for this tile
-    {
-        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
-        for (int c = tid; c < a.n_ch; c += 64 * NW) {
-            const double* ch = chan + 4 * c;
-            const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
-                             sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
-            int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
-            s = max(0, min(s, a.n_l - wpl));
-            win[c] = s & ~1;
-        }
-    }
+    const float kref_rev_f = static_cast<float>(kref_rev);
+    const float inv_du_f = static_cast<float>(a.inv_du);
+    const GatherTileEntry* tt = tab + static_cast<size_t>(tile) * a.n_ch;
 
     // DMA chunk offsets (bytes from the channel's window start), ~0 = idle
     unsigned doff[NIW];
@@ -322,8 +327,7 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const size_t chan_elems = static_cast<size_t>(a.n_z) * a.n_l;
 #define PL_STAGE_Q(C_, BUF_)                                                                          \
     do {                                                                                              \
-        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems +                     \
-                                                          __builtin_amdgcn_readfirstlane(win[C_]));   \
+        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems + tt[C_].win);       \
         unsigned char* dst_ = smem + lds_q + (BUF_) * kBufBytes;                                      \
         _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                                          \
             const int i_ = wave + NW * j_;                                                            \
@@ -331,10 +335,11 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         }                                                                                             \
     } while (0)
 
-    // this lane's pixel
+    // this lane's pixel and its offset from the tile centre
     const int px = tx0 + (lane & 7), py = ty0 + (lane >> 3);
     const bool pvalid = px < a.nx && py < a.ny;
-    const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
+    const float ox = ((lane & 7) - 3.5f) * static_cast<float>(a.dx), oy = ((lane >> 3) - 3.5f) * static_cast<float>(a.dy);
+    const float oo = ox * ox + oy * oy;
 
     // weights of (this lane's pixel, channel c) into slot [par][wave]:
     // five tap weights over the aligned samples (first tap's parity decides
@@ -344,14 +349,21 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         float cr = 0.f, ci = 0.f;
         int off = 0;
         if (c < a.n_ch && pvalid) {
-            const double* ch = chan + 4 * c;
-            const double l = sqrt((xg - ch[0]) * (xg - ch[0]) + (yg - ch[1]) * (yg - ch[1])) +
-                             sqrt((xg - ch[2]) * (xg - ch[2]) + (yg - ch[3]) * (yg - ch[3]));
-            const double u = (l - llo[c]) * a.inv_du;
-            const double fl = floor(u);
-            const float t = static_cast<float>(u - fl);
+            const GatherTileEntry& e = tt[c];   // wavefront-uniform
+            // range offset from the tile centre (see GatherTileEntry)
+            const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
+            float dl = sT * __builtin_amdgcn_rcpf(e.dt + sqrtf(e.dt * e.dt + sT));
+            if (a.mono) {
+                dl += dl;
+            } else {
+                const float sR = 2.f * (e.xr * ox + e.yr * oy) + oo;
+                dl += sR * __builtin_amdgcn_rcpf(e.dr + sqrtf(e.dr * e.dr + sR));
+            }
+            const float uu = e.uf + dl * inv_du_f;
+            const float fv = floorf(uu);
+            const float t = uu - fv;
             // the last chunk a pixel may read (past its taps) is staged too
-            const int i0 = max(0, min(static_cast<int>(fl) - 1 - win[c], wpl - 6));
+            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 6));
             const bool odd = i0 & 1;
             float v[4];
 #pragma unroll
@@ -362,9 +374,12 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             w[2] = odd ? v[1] : v[2];
             w[3] = odd ? v[2] : v[3];
             w[4] = odd ? v[3] : 0.f;
-            const float2 car = cis_rev(kref_rev * l);
-            cr = car.x;
-            ci = car.y;
+            // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
+            const float2 c0 = cis_rev(kref_rev * e.lc);
+            float sn, cs;
+            sincospif(2.f * (kref_rev_f * dl), &sn, &cs);
+            cr = c0.x * cs - c0.y * sn;
+            ci = c0.x * sn + c0.y * cs;
             off = (i0 & ~1) * 8;
         }
         float4* slot = wts + (par * NB + wave) * 2 * 64 + lane;
@@ -426,14 +441,47 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
 
 template <int KB, int RSC>
 __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(const float2* __restrict__ q,
-                                                                               const double* __restrict__ chan,
-                                                                               const double* __restrict__ llo,
+                                                                               const GatherTileEntry* __restrict__ tab,
                                                                                BpgArgs a, float2* __restrict__ G) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
     if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
     const int blk = work / a.n_tiles;
-    gather_tile<KB, RSC>(a, q, chan, llo, G, blk, work - blk * a.n_tiles, smem);
+    gather_tile<KB, RSC>(a, q, tab, G, blk, work - blk * a.n_tiles, smem);
+}
+
+// The tile table (see GatherTileEntry), one thread per (tile, channel).
+__global__ void gather_table_kernel(BpgArgs a, const double* __restrict__ chan, const double* __restrict__ llo,
+                                    GatherTileEntry* __restrict__ tab) {
+    const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
+    const int wpl = 2 * a.nchk;
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < n;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int tile = static_cast<int>(e / a.n_ch), c = static_cast<int>(e - static_cast<long long>(tile) * a.n_ch);
+        const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
+        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
+        const double* ch = chan + 4 * c;
+        const double xt = cx - ch[0], yt = cy - ch[1], xr = cx - ch[2], yr = cy - ch[3];
+        const double dt = sqrt(xt * xt + yt * yt), dr = sqrt(xr * xr + yr * yr);
+        const double l = dt + dr;
+        int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
+        s = max(0, min(s, a.n_l - wpl)) & ~1;
+        const double u = (l - llo[c]) * a.inv_du;
+        const double fl = floor(u);
+        GatherTileEntry t;
+        t.lc = l;
+        t.win = s;
+        t.base = static_cast<int>(fl) - 1 - s;
+        t.uf = static_cast<float>(u - fl);
+        t.xt = static_cast<float>(xt);
+        t.yt = static_cast<float>(yt);
+        t.dt = static_cast<float>(dt);
+        t.xr = static_cast<float>(xr);
+        t.yr = static_cast<float>(yr);
+        t.dr = static_cast<float>(dr);
+        t.pad_ = 0.f;
+        tab[e] = t;
+    }
 }
 
 // Persistent form for a batch of scans: eight work queues, one per XCD, each
@@ -460,8 +508,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_batch_ke
             if (it >= hi) break;
             const int4 w = items[it];
             const BatchScanDesc& d = scans[w.x];
-            gather_tile<KB, RSC>(d.a, reinterpret_cast<const float2*>(ws + d.q_off), d.chan,
-                                 reinterpret_cast<const double*>(ws + d.llo_off),
+            gather_tile<KB, RSC>(d.a, reinterpret_cast<const float2*>(ws + d.q_off),
+                                 reinterpret_cast<const GatherTileEntry*>(ws + d.tab_off),
                                  reinterpret_cast<float2*>(ws + d.g_off), w.y, w.z, smem);
             __syncthreads();  // LDS is reused by the next item
         }
@@ -694,14 +742,14 @@ int launch_adjoint_cfg(const AdjArgs& a, unsigned blocks, hipStream_t s, const f
 
 template <int KB, int RSC>
 int launch_gather(const BpgArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
-                  const double* chan, const double* llo, float2* G) {
+                  const GatherTileEntry* tab, float2* G) {
     auto fn = backproject_gather_kernel<KB, RSC>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
         if (e != hipSuccess) return fail(PL_EDEVICE, "back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kGatherWaves), smem, s, q, chan, llo, a, G);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kGatherWaves), smem, s, q, tab, a, G);
     return check_launch("back-projection (pixel per lane)");
 }
 
@@ -717,7 +765,7 @@ BpgArgs gather_args(const HybridPlan& p) {
     a.n_work = a.n_tiles * p.n_blocks;
     a.per_xcd = (a.n_work + 7) / 8;
     a.nchk = p.window / 2 + 1;  // staged chunks: the window and one more
-    a.win_bytes = ((p.n_ch + 3) & ~3) * 4;
+    a.mono = p.mode == PL_MONO;
     a.x0 = p.x0;
     a.y0 = p.y0;
     a.dx = p.dx;
@@ -756,12 +804,13 @@ int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, cha
     const BpgArgs a = gather_args(p);
     int rc = check_gather_plan(p, p.window_pad);
     if (rc) return rc;
-    const size_t smem = backproject_gather_lds_bytes(p.n_ch, p.block, p.window_pad);
+    const size_t smem = backproject_gather_lds_bytes(p.block, p.window_pad);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
-    const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
+    const GatherTileEntry* tab = reinterpret_cast<const GatherTileEntry*>(ws + p.off_tiles);
+    (void)dt;
 #define PL_G(KB, RSC) \
-    if (p.block == KB && p.window_pad == RSC) return launch_gather<KB, RSC>(a, smem, blocks, s, q, dt.chan, llo, G);
+    if (p.block == KB && p.window_pad == RSC) return launch_gather<KB, RSC>(a, smem, blocks, s, q, tab, G);
     PL_G(64, 12) PL_G(64, 16) PL_G(64, 20) PL_G(64, 24) PL_G(64, 33)
     PL_G(32, 12) PL_G(32, 16) PL_G(32, 20) PL_G(32, 24) PL_G(32, 33)
 #undef PL_G
@@ -772,14 +821,13 @@ int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, cha
 
 size_t gather_batch_desc_bytes() { return sizeof(BatchScanDesc); }
 
-int build_gather_batch_desc(const HybridPlan& p, const double* chan, size_t ws_off, int rsc, void* out) {
+int build_gather_batch_desc(const HybridPlan& p, size_t ws_off, int rsc, void* out) {
     int rc = check_gather_plan(p, rsc);
     if (rc) return rc;
     BatchScanDesc d{};
     d.a = gather_args(p);
-    d.chan = chan;
     d.q_off = ws_off + p.off_q;
-    d.llo_off = ws_off + p.off_llo;
+    d.tab_off = ws_off + p.off_tiles;
     d.g_off = ws_off + p.off_G;
     std::memcpy(out, &d, sizeof(d));
     return PL_OK;
@@ -855,8 +903,22 @@ int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, cons
                          : launch_adjoint_cfg<64>(a, blocks, s, Gt, dt.chan, llo, qt);
 }
 
-size_t backproject_gather_lds_bytes(int n_ch, int rows, int row_chunks) {
-    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + 2ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
+size_t backproject_gather_lds_bytes(int rows, int row_chunks) {
+    return 2ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
+}
+
+size_t gather_table_bytes(const HybridPlan& p) {
+    return static_cast<size_t>(p.tiles_x) * p.tiles_y * p.n_ch * sizeof(GatherTileEntry);
+}
+
+int launch_gather_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s) {
+    if (!p.bp_gather) return PL_OK;
+    const BpgArgs a = gather_args(p);
+    const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
+    const int blocks = static_cast<int>(std::min<long long>((n + 255) / 256, 8192));
+    hipLaunchKernelGGL(gather_table_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan,
+                       reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<GatherTileEntry*>(ws + p.off_tiles));
+    return check_launch("back-projection tile table");
 }
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad) {

@@ -207,7 +207,8 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
                        reinterpret_cast<float2*>(ws + p.off_tw_scan),
                        reinterpret_cast<float2*>(ws + p.off_tw_fine), reinterpret_cast<float*>(ws + p.off_deap),
                        reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk));
-    return check_launch("plan tables");
+    const int rc = check_launch("plan tables");
+    return rc ? rc : launch_gather_tables(p, dt, ws, s);
 }
 
 int launch_twiddles(float2* tw, int n, hipStream_t s) {

@@ -209,7 +209,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
             int rsc = 0;
             for (int r : rows)
                 if (!rsc && nchk + 1 <= r) rsc = r;
-            if (rsc && backproject_gather_lds_bytes(p.n_ch, p.block, rsc) <= kMaxLds) {
+            if (rsc && backproject_gather_lds_bytes(p.block, rsc) <= kMaxLds) {
                 p.bp_gather = true;
                 p.tile_x = p.tile_y = 8;
                 p.window = 2 * nchk;   // samples staged per row
@@ -341,6 +341,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_deap = take(static_cast<size_t>(p.n_l) * 4);
     p.off_kp = take(nz * nf * 8);
     p.off_wk = take(nz * nf * 4);
+    p.off_tiles = take(p.bp_gather ? gather_table_bytes(p) : 0);
     p.n_chp = (p.n_ch + 31) / 32 * 32;
     p.n_fp = (p.n_f + 15) / 16 * 16;
     if (p.precision != PL_PREC_FP32) {
