@@ -115,7 +115,7 @@ def main() -> int:
     ap.add_argument("--bp-planes", type=int, default=2)
     ap.add_argument("--tile", type=int, default=0, help="back-projection tile (0 = automatic)")
     ap.add_argument("--interp", default="bspline4", choices=["bspline4", "lagrange4", "linear"])
-    ap.add_argument("--l-oversample", type=float, default=8.0)
+    ap.add_argument("--l-oversample", type=float, default=6.0)
     ap.add_argument("--kz-per-lane", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1],

@@ -189,7 +189,7 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *   precision     PL_PREC_* (default FP32).
  *   interp        PL_INTERP_* (default cubic B-spline).
  *   l_oversample  range-grid oversampling over the Nyquist rate of the
- *                 baseband range profile (default 8; >= 2).
+ *                 baseband range profile (default 6; >= 2).
  *   nufft_tol     NUFFT tolerance (default 1e-6; 1e-12 .. 1e-2).
  * The FP32 back-projection (VALU) has two kernels.  By default one pixel of
  * an 8x8 tile per lane (PL_BP_PIXEL_LANES); where the tile's range window

@@ -211,7 +211,7 @@ def _grid(grid) -> ImageGridC:
                       float(grid.dy))
 
 
-def _opts(precision="fp32", interp="bspline4", l_oversample=8.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
+def _opts(precision="fp32", interp="bspline4", l_oversample=6.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
           waves=0, mfma_backprojection=0, tile_y=0, kz_block=0, range_method="nufft") -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")

@@ -76,7 +76,7 @@ struct HybridPlan {
     int nx = 0, ny = 0;
     double x0 = 0, y0 = 0, dx = 0, dy = 0;
     int precision = PL_PREC_FP32, interp = PL_INTERP_BSPLINE4;
-    double sigma_l = 8.0, tol = 1e-6;
+    double sigma_l = 6.0, tol = 1e-6;
     int force_tile = 0, force_tile_y = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0, force_kb = 0;
     bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
     bool bp_gather = false;          // VALU back-projection with one pixel per lane

@@ -96,7 +96,7 @@ def test_plan_is_consistent(wl):
         kr = np.sqrt(np.maximum(kf[None] ** 2 - kk[:, None] ** 2 / 4, 0))
         kr = kr[kr > 0]
         half = max(half, (kr.max() - kr.min()) / 2)
-    assert math.isclose(p.du, math.pi / (8 * half), rel_tol=1e-12)
+    assert math.isclose(p.du, math.pi / (6 * half), rel_tol=1e-12)   # default l_oversample 6
     assert pr.hybrid_workspace_bytes(g, wl.grid) == p.workspace_bytes
     assert p.workspace_bytes >= 8 * (arr.n_channels * wl.array.n_scan * (wl.array.n_freq + p.n_l))
 
@@ -215,7 +215,7 @@ def test_valu_backprojection_plan_rules():
     assert pr.hybrid_plan_info(g, W.C2.grid, kz_per_lane=1).bp_kernel == "kz-lanes"
     assert pr.hybrid_plan_info(g, W.C2.grid, tile=4).bp_kernel == "kz-lanes"
     # pixels too coarse for 64 staged samples: the k_z-per-lane kernel on smaller tiles
-    p1 = pr.hybrid_plan_info(pr.make_geometry(W.C1.array), W.C1.grid)
+    p1 = pr.hybrid_plan_info(pr.make_geometry(W.C1.array), W.ImageGrid.centred(16, 0.30))
     assert p1.bp_kernel == "kz-lanes" and p1.tile == (4, 4)
 
 
@@ -279,9 +279,9 @@ def test_autotune_candidates_and_cache(tmp_path):
     cb = at.candidates(g, W.C2.grid, "bf16")
     assert any(o.get("mfma_backprojection") for o in cb) and len(cb) > len(c32)
     # coarse pixels: every request maps to the k_z-per-lane kernel, listed once per shape
-    g1 = pr.make_geometry(W.C1.array)
-    c1 = at.candidates(g1, W.C1.grid, "fp32")
-    shapes = [(p.bp_kernel, p.tile, p.block, p.waves) for p in (pr.hybrid_plan_info(g1, W.C1.grid, **o) for o in c1)]
+    g1, coarse = pr.make_geometry(W.C1.array), W.ImageGrid.centred(16, 0.30)
+    c1 = at.candidates(g1, coarse, "fp32")
+    shapes = [(p.bp_kernel, p.tile, p.block, p.waves) for p in (pr.hybrid_plan_info(g1, coarse, **o) for o in c1)]
     assert len(shapes) == len(set(shapes)) and all(s[0] == "kz-lanes" for s in shapes)
     # a cached entry is returned without timing anything
     cache = str(tmp_path / "tune.json")

@@ -431,7 +431,7 @@ def _small_batch():
         (c1.array, _fine_grid(45, 29, 0.003), {}),
         (replace(c1.array, n_scan=30, n_freq=20), _fine_grid(21, 40, 0.004), {}),
         (ms.array, _fine_grid(27, 35, 0.004), {}),
-        (c1.array, c1.grid, {}),                                              # coarse: k_z per lane
+        (c1.array, W.ImageGrid.centred(16, 0.30), {}),                        # coarse: k_z per lane
         (replace(c1.array, n_scan=32), _fine_grid(40, 40, 0.0015), dict(precision="bf16", mfma_backprojection=1)),
     ]
     return scans
@@ -640,8 +640,8 @@ def evanescent_small():
 def test_resample_range_method_matches_oracle(wlname):
     # random echoes fill the whole unambiguous range, so the method's own
     # error (interpolating the demodulated spectrum) is large here; the
-    # oracle of the same method is the reference.  The "-fine" grids take
-    # the pixel-per-lane back-projection, the others the k_z-per-lane one.
+    # oracle of the same method is the reference.  Each case runs the
+    # automatic back-projection and the k_z-per-lane one.
     wl = {"tiny-mono": W.tiny("mono"), "tiny-multi": W.tiny("multi"), "multi-small": multi_small(),
           "C1": W.C1, "evanescent-small": evanescent_small(),
           "C1-fine": replace(W.C1, grid=_fine_grid(45, 29, 0.003)),
