@@ -29,10 +29,11 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
 
 
-def measured_traffic(kernel: str, workload: str, precision: str):
+def measured_traffic(kernel: str, workload: str, precision: str, n_l: int):
     """HBM bytes per back-projection launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
-    kernel and workload or the kernel source changed since it was taken."""
+    kernel, workload and range grid, or the kernel source changed since it
+    was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "backproject_c2_hbm_traffic.md")
     if not os.path.exists(path):
@@ -41,7 +42,8 @@ def measured_traffic(kernel: str, workload: str, precision: str):
         if not line.startswith("traffic:"):
             continue
         f = dict(kv.split("=", 1) for kv in line.split()[1:])
-        if (f.get("kernel"), f.get("workload"), f.get("precision")) != (kernel, workload, precision):
+        if (f.get("kernel"), f.get("workload"), f.get("precision"), f.get("n_l")) != (kernel, workload, precision,
+                                                                                      str(n_l)):
             continue
         src = os.path.join(ROOT, f["source"])
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != f["sha256"]:
@@ -67,7 +69,11 @@ def describe(wl) -> str:
 
 def cpu_baseline(wl, echo_np, budget_s=12.0):
     """The FP64 oracle timed on a bounded sample of the same workload: the
-    exact spectrum at a few (k_z, pixel) pairs, extrapolated to the image."""
+    exact spectrum at a sample of (k_z, pixel) pairs, split over host threads
+    (numpy releases the interpreter lock in its array kernels; one BLAS thread
+    per call), extrapolated to the image."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from threadpoolctl import threadpool_limits
 
     from oracle import geometry as ogeom
@@ -78,28 +84,55 @@ def cpu_baseline(wl, echo_np, budget_s=12.0):
     npix = wl.grid.nx * wl.grid.ny
     px, py = ohyb.pixel_grid(wl.grid)
     S = ohyb.scan_spectrum(echo_np)   # the FFTs: negligible next to the sums
-    n_pix = 256
-    kap = [0]
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def run(pix, kap):
+        chunks = [c for c in np.array_split(pix, threads) if c.size]
+        with ThreadPoolExecutor(len(chunks)) as ex:
+            t0 = time.perf_counter()
+            list(ex.map(lambda c: ohyb.spectrum_at(arr, S, kap, px[c], py[c]), chunks))
+            return time.perf_counter() - t0
+
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        pix = W.random_subset(npix, n_pix, 99)
-        ohyb.spectrum_at(arr, S, kap, px[pix], py[pix])
-        dt = time.perf_counter() - t0
-        # grow the sample to about budget_s of CPU work
+        n_pix = 256 * threads
+        kap = [0]
+        dt = run(W.random_subset(npix, n_pix, 99), kap)
+        # grow the sample to about budget_s of wall time
         scale = max(1, min(64, int(budget_s / max(dt, 1e-3))))
         pix = W.random_subset(npix, min(npix, n_pix * scale), 98)
         kap = [0, wl.array.n_scan // 3] if pix.size == npix else [0]
-        t0 = time.perf_counter()
-        ohyb.spectrum_at(arr, S, kap, px[pix], py[pix])
-        dt = time.perf_counter() - t0
+        dt = run(pix, kap)
     pairs = len(kap) * pix.size
     total_pairs = wl.array.n_scan * npix
     t_full = dt * total_pairs / pairs
     vox = npix * wl.array.n_scan
-    return {"value": vox / t_full, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+    return {"value": vox / t_full, "unit": "voxels/s", "cores": threads, "kind": "oracle",
             "sample": (f"exact spectrum (eq. 7 direct sums) at {pairs} (k_z, pixel) pairs of "
-                       f"{total_pairs}, {dt:.1f} s on 1 thread, extrapolated linearly; "
+                       f"{total_pairs}, {dt:.1f} s on {threads} host threads, extrapolated linearly; "
                        f"scan FFTs excluded")}
+
+
+def peak_error(pr, torch, W, wl, geom, opts):
+    """Peak-position error on isolated point targets: three scatterers at
+    seeded voxel centres of this workload's grid and scan, simulated on the
+    GPU; for each, the distance in voxels from its true voxel to the largest
+    |g| within 4 voxels of it.  Returns the largest of the three."""
+    a, grid = wl.array, wl.grid
+    rng = np.random.default_rng(7)
+    ix = rng.integers(grid.nx // 4, 3 * grid.nx // 4, 3)
+    iy = rng.integers(grid.ny // 4, 3 * grid.ny // 4, 3)
+    iz = rng.integers(a.n_scan // 4, 3 * a.n_scan // 4, 3)
+    pos = np.stack([grid.x0 + ix * grid.dx, grid.y0 + iy * grid.dy, a.z0 + iz * a.scan_step], axis=1)
+    refl = np.ones(3, dtype=np.complex128)
+    echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
+    img = pr.reconstruct_hybrid(geom, grid, echo, **opts).abs().cpu().numpy()
+    worst = 0.0
+    for x, y, z in zip(ix, iy, iz):
+        z0, y0, x0 = max(z - 4, 0), max(y - 4, 0), max(x - 4, 0)
+        box = img[z0:z + 5, y0:y + 5, x0:x + 5]
+        k = np.unravel_index(np.argmax(box), box.shape)
+        worst = max(worst, float(np.sqrt((k[0] + z0 - z) ** 2 + (k[1] + y0 - y) ** 2 + (k[2] + x0 - x) ** 2)))
+    return worst
 
 
 def main() -> int:
@@ -250,7 +283,7 @@ def main() -> int:
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
                    "tile": list(plan.tile), "kz_block": plan.block},
         "roofline": dict(roof, unit="TFLOP/s",
-                         traffic=measured_traffic(plan.bp_kernel, args.config, args.precision),
+                         traffic=measured_traffic(plan.bp_kernel, args.config, args.precision, plan.n_l),
                          kernel="backproject", flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
         "stages_ms": stage,
         "plan_build_ms": first_ms,
@@ -259,6 +292,9 @@ def main() -> int:
         err, sample = parity(opts)
         out["rel_l2_vs_oracle"] = {"value": err, "sample": sample, "echo": "seeded CN(0,1)"}
         log(f"[bench] {args.precision}: rel L2 vs oracle {err:.2e} ({sample})")
+        pk = peak_error(pr, torch, W, wl, geom, opts)
+        out["peak_position_error_voxels"] = pk
+        log(f"[bench] {args.precision}: peak-position error {pk:.2f} voxels (3 point targets)")
     if not args.no_variants:
         out["variants"] = {}
         for name, prec, mbp, rm in (("bf16", "bf16", 0, "nufft"), ("fp16", "fp16", 0, "nufft"),
