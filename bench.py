@@ -213,21 +213,30 @@ def main() -> int:
             pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
+        # the timed steps: plain calls, one event between consecutive calls
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        for e in marks:
+            e.record(stream)   # creates the underlying hipEvent
+        torch.cuda.synchronize()
+        marks[0].record(stream)
+        for k in range(steps):
+            pr.reconstruct_hybrid(geom, wl.grid, echo, out=img, ws=ws, **opts)
+            marks[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = marks[0].elapsed_time(marks[steps]) / steps
+        steps_ms = [marks[k].elapsed_time(marks[k + 1]) for k in range(steps)]
+        # a second pass with events between the stages, for the breakdown and
+        # the back-projection's launch duration
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for row in evs:
             for e in row:
-                e.record(stream)   # creates the underlying hipEvent
+                e.record(stream)
         torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record(stream)
         for k in range(steps):
             pr.reconstruct_hybrid_events(geom, wl.grid, echo, evs[k], out=img, ws=ws, **opts)
-        stop.record(stream)
         torch.cuda.synchronize()
-        ms = start.elapsed_time(stop) / steps
         stage = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
                  for i, name in enumerate(pr.STAGES)}
-        steps_ms = [evs[k][0].elapsed_time(evs[k][5]) for k in range(steps)]
         del ws
         return ms, stage, first_ms, float(np.median(steps_ms)), plan
 
