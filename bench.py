@@ -67,7 +67,7 @@ def describe(wl) -> str:
             f"{wl.scene.n} {wl.scene.kind} scatterers (seed {wl.scene.seed})")
 
 
-def cpu_baseline(wl, echo_np, budget_s=12.0):
+def cpu_baseline(wl, echo_np, budget_s=20.0):
     """The FP64 oracle timed on a bounded sample of the same workload: the
     exact spectrum at a sample of (k_z, pixel) pairs, split over host threads
     (numpy releases the interpreter lock in its array kernels; one BLAS thread
@@ -94,13 +94,17 @@ def cpu_baseline(wl, echo_np, budget_s=12.0):
             return time.perf_counter() - t0
 
     with threadpool_limits(limits=1):
-        n_pix = 256 * threads
-        kap = [0]
-        dt = run(W.random_subset(npix, n_pix, 99), kap)
-        # grow the sample to about budget_s of wall time
-        scale = max(1, min(64, int(budget_s / max(dt, 1e-3))))
-        pix = W.random_subset(npix, min(npix, n_pix * scale), 98)
-        kap = [0, wl.array.n_scan // 3] if pix.size == npix else [0]
+        n_pix = min(npix, 256 * threads)
+        dt = run(W.random_subset(npix, n_pix, 99), [0])
+        # grow the sample to about budget_s of wall time: more pixels, then
+        # more k_z planes of the whole image
+        target = budget_s / max(dt / n_pix, 1e-9)
+        if target <= npix:
+            pix, kap = W.random_subset(npix, max(n_pix, int(target)), 98), [0]
+        else:
+            n_kap = max(1, min(wl.array.n_scan, int(target // npix)))
+            pix = np.arange(npix)
+            kap = sorted(set(W.random_subset(wl.array.n_scan, n_kap, 97).tolist()))
         dt = run(pix, kap)
     pairs = len(kap) * pix.size
     total_pairs = wl.array.n_scan * npix
