@@ -202,8 +202,9 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 1, 2, 4.  64 x kz_per_lane bins share one reference
  *                 wavenumber, so this also sets the range-grid step.
  *   kz_block      k_z bins per workgroup (one reference wavenumber): 0 =
- *                 automatic (64); pixel-per-lane kernel 32 or 64, MFMA kernel
- *                 64 or 128.
+ *                 automatic (32 for the pixel-per-lane kernel, 64 for the
+ *                 others); pixel-per-lane kernel 32 or 64, MFMA kernel 64 or
+ *                 128.
  *   waves         wavefronts per back-projection workgroup: 0 = automatic, or
  *                 4, 8 (VALU: 8 selects the k_z-per-lane kernel on the 8x8
  *                 tile; MFMA: 8 only with the 16x8 and 16x16 tiles).
