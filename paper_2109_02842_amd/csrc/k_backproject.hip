@@ -376,10 +376,9 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             w[4] = odd ? v[3] : 0.f;
             // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
             const float2 c0 = cis_rev(kref_rev * e.lc);
-            float sn, cs;
-            sincospif(2.f * (kref_rev_f * dl), &sn, &cs);
-            cr = c0.x * cs - c0.y * sn;
-            ci = c0.x * sn + c0.y * cs;
+            const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
+            cr = c0.x * c1.x - c0.y * c1.y;
+            ci = c0.x * c1.y + c0.y * c1.x;
             off = (i0 & ~1) * 8;
         }
         float4* slot = wts + (par * NB + wave) * 2 * 64 + lane;
