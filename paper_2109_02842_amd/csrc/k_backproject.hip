@@ -352,12 +352,12 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             const GatherTileEntry& e = tt[c];   // wavefront-uniform
             // range offset from the tile centre (see GatherTileEntry)
             const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
-            float dl = sT * __builtin_amdgcn_rcpf(e.dt + sqrtf(e.dt * e.dt + sT));
+            float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
             if (a.mono) {
                 dl += dl;
             } else {
                 const float sR = 2.f * (e.xr * ox + e.yr * oy) + oo;
-                dl += sR * __builtin_amdgcn_rcpf(e.dr + sqrtf(e.dr * e.dr + sR));
+                dl += sR * __builtin_amdgcn_rcpf(e.dr + __builtin_amdgcn_sqrtf(e.dr * e.dr + sR));
             }
             const float uu = e.uf + dl * inv_du_f;
             const float fv = floorf(uu);

@@ -77,13 +77,13 @@ __global__ __launch_bounds__(256) void nufft_kernel(const float2* __restrict__ s
             const double d = k - py[f];
             if (d <= -a.h) break;
             const float z = static_cast<float>(d * a.inv_h);
-            const float phi = __expf(static_cast<float>(a.beta) * (sqrtf(fmaxf(1.f - z * z, 0.f)) - 1.f));
+            const float phi = __expf(static_cast<float>(a.beta) * (__builtin_amdgcn_sqrtf(fmaxf(1.f - z * z, 0.f)) - 1.f));
             acc.x += pa[f].x * phi;
             acc.y += pa[f].y * phi;
         }
-        int kk = k % a.n_fine;
-        if (kk < 0) kk += a.n_fine;
-        A[kk] = acc;
+        // the points lie within half the fine grid of cell 0 (|k' du| <= pi / sigma),
+        // so every cell index is within one period of [0, n_fine)
+        A[k < 0 ? k + a.n_fine : (k >= a.n_fine ? k - a.n_fine : k)] = acc;
     }
     __syncthreads();
     const float2* res = lds_fft(A, B, a.n_fine, a.n_fine, 1, a.rad, tw, +1, tid, blockDim.x);
