@@ -311,6 +311,22 @@ int reconstruct_hybrid(const pl_geometry* geom, const pl_image_grid* grid,
                        void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Plan caching.  hybrid_prepare writes the plan's device tables (range-grid
+ * origins, reference ranges, twiddles, deapodisation, k' and weight tables,
+ * the back-projection's tile geometry) into ws; they depend on the geometry,
+ * grid and options only.  reconstruct_hybrid_prepared is reconstruct_hybrid
+ * without that step: ws must hold the tables of a hybrid_prepare call with
+ * the same geometry, grid and options on the same device, and no other call
+ * may have used ws since (the reconstruction itself leaves them intact).
+ * Results are bitwise those of reconstruct_hybrid.  Same errors.
+ */
+int hybrid_prepare(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws,
+                   size_t ws_bytes, hipStream_t stream);
+int reconstruct_hybrid_prepared(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                                const float* echo_dev, float* image_dev, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/*
  * reconstruct_hybrid with stage timing for profilers: records
  * stage_events[i] on the stream before stage i and stage_events[5] after the
  * last stage.  Stages: 0 plan tables, 1 scan FFT, 2 range compression,

@@ -85,6 +85,9 @@ _SIGNATURES = {
                                          C.POINTER(C.c_size_t)]),
     "reconstruct_hybrid": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                                      C.c_size_t, _P]),
+    "reconstruct_hybrid_prepared": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
+                                              C.c_size_t, _P]),
+    "hybrid_prepare": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, C.c_size_t, _P]),
     "adjoint_hybrid": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                                  C.c_size_t, _P]),
     "reconstruct_hybrid_events": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P,
@@ -338,18 +341,34 @@ def simulate_echo(geom: Geometry, xyz, refl, out=None):
     return out
 
 
-def reconstruct_hybrid(geom: Geometry, grid, echo, out=None, ws=None, **opts):
-    """Image g[z][y][x] (complex64) by the hybrid method of Sec. II."""
+def reconstruct_hybrid(geom: Geometry, grid, echo, out=None, ws=None, prepared=False, **opts):
+    """Image g[z][y][x] (complex64) by the hybrid method of Sec. II.
+
+    prepared=True skips the plan tables: ``ws`` must hold them from
+    ``hybrid_prepare`` with the same geometry, grid and options."""
     torch = _torch()
     need = hybrid_workspace_bytes(geom, grid, **opts)
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the workspace hybrid_prepare filled")
     ws = _ws(ws, need)
     shape = (geom.n_scan, grid.ny, grid.nx)
     if out is None:
         out = torch.empty(shape, dtype=torch.complex64, device=echo.device)
-    _check(lib().reconstruct_hybrid(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
-                                    _dev_c64(echo, geom.echo_shape, "echo"), _dev_c64(out, shape, "out"),
-                                    C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    fn = lib().reconstruct_hybrid_prepared if prepared else lib().reconstruct_hybrid
+    _check(fn(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
+              _dev_c64(echo, geom.echo_shape, "echo"), _dev_c64(out, shape, "out"),
+              C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
+
+
+def hybrid_prepare(geom: Geometry, grid, ws=None, **opts):
+    """Write the plan's device tables into a workspace (returned) for
+    reconstruct_hybrid(..., prepared=True)."""
+    need = hybrid_workspace_bytes(geom, grid, **opts)
+    ws = _ws(ws, need)
+    _check(lib().hybrid_prepare(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return ws
 
 
 # ------------------------------------------------------------------ batches

@@ -183,10 +183,15 @@ int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectr
     return launch_kz_ifft(p, reinterpret_cast<const float2*>(spectrum), reinterpret_cast<float2*>(image), tw, stream);
 }
 
-int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
-                              const float* echo, float* image, void* ws, size_t ws_bytes, hipEvent_t* ev,
-                              hipStream_t stream) {
-    using namespace pl;
+}  // extern "C"
+
+namespace pl {
+namespace {
+
+// The hybrid reconstruction; tables = false skips the plan-table step (the
+// caller prepared the workspace with hybrid_prepare for the same arguments).
+int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
+                     float* image, void* ws, size_t ws_bytes, hipEvent_t* ev, hipStream_t stream, bool tables) {
     clear_error();
     if (!echo || !image) return fail(PL_EINVAL, "reconstruct_hybrid: null echo or image");
     HybridPlan p;
@@ -203,7 +208,7 @@ int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, c
     float2* q = reinterpret_cast<float2*>(w + p.off_q);
     float2* G = reinterpret_cast<float2*>(w + p.off_G);
     const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
-    if ((rc = mark(0)) || (rc = launch_plan_tables(p, dt, w, stream))) return rc;
+    if ((rc = mark(0)) || (tables && (rc = launch_plan_tables(p, dt, w, stream)))) return rc;
     if ((rc = mark(1)) ||
         (rc = launch_scan_fft(g, reinterpret_cast<const float2*>(echo), spec, tw_scan, p.scan_rad, stream)))
         return rc;
@@ -223,9 +228,36 @@ int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, c
     return mark(5);
 }
 
+}  // namespace
+}  // namespace pl
+
+extern "C" {
+
+int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                              const float* echo, float* image, void* ws, size_t ws_bytes, hipEvent_t* ev,
+                              hipStream_t stream) {
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, ev, stream, true);
+}
+
 int reconstruct_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
                        float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
-    return reconstruct_hybrid_events(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream);
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, true);
+}
+
+int hybrid_prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws,
+                   size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    HybridPlan p;
+    DeviceTables dt;
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "hybrid_prepare");
+    if (rc) return rc;
+    return launch_plan_tables(p, dt, static_cast<char*>(ws), stream);
+}
+
+int reconstruct_hybrid_prepared(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                                const float* echo, float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, false);
 }
 
 int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* image,

@@ -334,6 +334,22 @@ def test_hybrid_c1_point_targets():
     assert np.unravel_index(np.argmax(a), a.shape) == np.unravel_index(np.argmax(b), b.shape)
 
 
+@pytest.mark.parametrize("opts", [{}, dict(precision="bf16", mfma_backprojection=1), dict(range_method="resample")],
+                         ids=["fp32", "bf16-mfma-bp", "resample"])
+def test_prepared_plan_matches_plain_call(opts):
+    # the plan tables written once by hybrid_prepare serve later calls; the
+    # result is bitwise that of the call that builds them itself
+    wl = W.C2
+    g = pr.make_geometry(wl.array)
+    s = dev(W.random_echo(wl.array, 31))
+    ws = pr.hybrid_prepare(g, wl.grid, **opts)
+    a = host(pr.reconstruct_hybrid(g, wl.grid, s, ws=ws, prepared=True, **opts))
+    b = host(pr.reconstruct_hybrid(g, wl.grid, s, ws=ws, prepared=True, **opts))   # tables survive a call
+    c = host(pr.reconstruct_hybrid(g, wl.grid, s, **opts))
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+    assert np.array_equal(b.view(np.uint32), c.view(np.uint32))
+
+
 def test_hybrid_is_deterministic():
     wl = W.C1
     g = pr.make_geometry(wl.array)
