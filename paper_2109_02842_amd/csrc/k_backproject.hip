@@ -242,8 +242,8 @@ int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s
 // Pixel-per-lane variant (the default): one workgroup = one 8x8 pixel tile x
 // KB k_z bins; lane = pixel, wavefront w owns k_z rows [RW w, RW (w + 1)).
 // The weights and carrier of a (pixel, channel) pair are computed once per
-// workgroup (wavefront w for the w-th channel of a batch of 4, one batch
-// ahead) and shared through LDS, so nothing is broadcast per pixel.  Every
+// workgroup (wavefront w for the w-th channel of a batch of 4, at the start
+// of the batch) and shared through LDS, so nothing is broadcast per pixel.  Every
 // LDS read is a 16-byte aligned ds_read_b128 (8-byte aligned pairs run at
 // about half the rate on gfx950): a pixel reads the aligned samples
 // [2m, 2m + 5) around its four taps (two 16-byte reads and one 8-byte read,
@@ -251,7 +251,9 @@ int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s
 // tap (one of them zero), so a (pixel, k_z) term costs 40 bytes of LDS and
 // fourteen FMAs.  The channel's window rows (even start)
 // are copied into LDS by 16-byte direct global-to-LDS loads one channel
-// ahead, double-buffered.
+// ahead, double-buffered.  The kernel is bound by instruction issue with
+// its latencies covered by other workgroups: LDS per workgroup (8 KiB of
+// weight slots and the two row buffers) is what sets how many fit a CU.
 struct BpgArgs {
     int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nchk, mono;
     double x0, y0, dx, dy, inv_du, reach;
@@ -303,8 +305,8 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
     constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
     constexpr unsigned kBufBytes = KB * RSC * 16;
-    float4* wts = reinterpret_cast<float4*>(smem);   // [2][NB][2][64]
-    constexpr unsigned lds_q = 2 * NB * 2 * 64 * 16;
+    float4* wts = reinterpret_cast<float4*>(smem);   // [NB][2][64]
+    constexpr unsigned lds_q = NB * 2 * 64 * 16;
 
     const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -325,9 +327,9 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         doff[j] = (r < KB && k < a.nchk) ? static_cast<unsigned>((kz * a.n_l + 2 * k) * 8) : ~0u;
     }
     const size_t chan_elems = static_cast<size_t>(a.n_z) * a.n_l;
-#define PL_STAGE_Q(C_, BUF_)                                                                          \
+#define PL_STAGE_Q(C_, BUF_, WIN_)                                                                    \
     do {                                                                                              \
-        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems + tt[C_].win);       \
+        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems + (WIN_));           \
         unsigned char* dst_ = smem + lds_q + (BUF_) * kBufBytes;                                      \
         _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                                          \
             const int i_ = wave + NW * j_;                                                            \
@@ -341,10 +343,10 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const float ox = ((lane & 7) - 3.5f) * static_cast<float>(a.dx), oy = ((lane >> 3) - 3.5f) * static_cast<float>(a.dy);
     const float oo = ox * ox + oy * oy;
 
-    // weights of (this lane's pixel, channel c) into slot [par][wave]:
+    // weights of (this lane's pixel, channel c) into slot [wave]:
     // five tap weights over the aligned samples (first tap's parity decides
     // the shift), carrier, byte offset of the first chunk in the row
-    auto weights = [&](int c, int par) {
+    auto weights = [&](int c) {
         float w[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         float cr = 0.f, ci = 0.f;
         int off = 0;
@@ -381,7 +383,7 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             ci = c0.x * c1.y + c0.y * c1.x;
             off = (i0 & ~1) * 8;
         }
-        float4* slot = wts + (par * NB + wave) * 2 * 64 + lane;
+        float4* slot = wts + wave * 2 * 64 + lane;
         slot[0] = make_float4(w[0], w[1], w[2], w[3]);
         slot[64] = make_float4(w[4], cr, ci, __int_as_float(off));
     };
@@ -390,22 +392,27 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
 #pragma unroll
     for (int r = 0; r < RW; ++r) acc[r] = make_float2(0.f, 0.f);
 
-    __syncthreads();  // window starts visible
-    weights(wave, 0);
-    PL_STAGE_Q(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    __syncthreads();  // LDS free (the batch kernel reuses it per item)
+    PL_STAGE_Q(0, 0, tt[0].win);
 
     const unsigned row0 = static_cast<unsigned>(wave * RW * RSC * 16);
 #pragma unroll 1
-    for (int c0 = 0, par = 0; c0 < a.n_ch; c0 += NB, par ^= 1) {
+    for (int c0 = 0; c0 < a.n_ch; c0 += NB) {
+        // window starts of the channels staged during this batch (lane k:
+        // channel c0 + 1 + k), one load per batch, read back by readlane
+        const int ck = c0 + 1 + lane;
+        const int wins = lane < NB && ck < a.n_ch ? tt[ck].win : 0;
+        // the previous batch's slots are read (barrier at the end of its
+        // last channel), so this batch's weights can take them
+        weights(c0 + wave);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
 #pragma unroll 1
         for (int cc = 0; cc < NB; ++cc) {
             const int c = c0 + cc;
             if (c >= a.n_ch) break;
-            if (c + 1 < a.n_ch) PL_STAGE_Q(c + 1, (c + 1) & 1);
-            if (cc == 0 && c0 + NB < a.n_ch) weights(c0 + NB + wave, par ^ 1);
-            const float4* slot = wts + (par * NB + cc) * 2 * 64 + lane;
+            if (c + 1 < a.n_ch) PL_STAGE_Q(c + 1, (c + 1) & 1, __builtin_amdgcn_readlane(wins, cc));
+            const float4* slot = wts + cc * 2 * 64 + lane;
             const float4 wa = slot[0], wb = slot[64];
             const unsigned off = __float_as_uint(wb.w);
             const unsigned char* rp = smem + lds_q + (c & 1) * kBufBytes + row0 + off;
@@ -494,15 +501,18 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_batch_ke
     const BatchScanDesc* __restrict__ scans, const int4* __restrict__ items, const int* __restrict__ bounds,
     unsigned* __restrict__ counters, char* __restrict__ ws) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ int next;
+    // the item index travels in the first word of the weight slots, which
+    // are free between items (no static LDS: it would cost a workgroup per
+    // CU at row lengths that fill the LDS exactly)
+    int* next = reinterpret_cast<int*>(smem);
     const int home = blockIdx.x & 7;
     for (int k = 0; k < 8; ++k) {
         const int x = (home + k) & 7;
         const int lo = bounds[x], hi = bounds[x + 1];
         for (;;) {
-            if (threadIdx.x == 0) next = lo + static_cast<int>(atomicAdd(counters + x, 1u));
+            if (threadIdx.x == 0) *next = lo + static_cast<int>(atomicAdd(counters + x, 1u));
             __syncthreads();
-            const int it = next;
+            const int it = *next;
             __syncthreads();  // every thread has read `next` before it is overwritten
             if (it >= hi) break;
             const int4 w = items[it];
@@ -785,6 +795,12 @@ int check_gather_plan(const HybridPlan& p, int rsc) {
     return PL_OK;
 }
 
+// Compiled (k_z bins, row chunks) classes of the pixel-per-lane kernels; the
+// row lengths are the longest at each occupancy level with 32 bins (LDS
+// 8 KiB + 2 KiB per chunk: 8, 7, 6, 5, 4 and 3 workgroups per CU).
+#define PL_GATHER_CLASSES(X) \
+    X(64, 12) X(64, 14) X(64, 18) X(64, 24) X(64, 32) X(64, 40) X(32, 12) X(32, 14) X(32, 18) X(32, 24) X(32, 32) X(32, 40)
+
 template <int KB, int RSC>
 const void* gather_batch_fn() {
     return reinterpret_cast<const void*>(backproject_gather_batch_kernel<KB, RSC>);
@@ -793,8 +809,7 @@ const void* gather_batch_fn() {
 const void* gather_batch_kernel(int kb, int rsc) {
 #define PL_GB(KB, RSC) \
     if (kb == KB && rsc == RSC) return gather_batch_fn<KB, RSC>();
-    PL_GB(64, 12) PL_GB(64, 16) PL_GB(64, 20) PL_GB(64, 24) PL_GB(64, 33)
-    PL_GB(32, 12) PL_GB(32, 16) PL_GB(32, 20) PL_GB(32, 24) PL_GB(32, 33)
+    PL_GATHER_CLASSES(PL_GB)
 #undef PL_GB
     return nullptr;
 }
@@ -810,8 +825,7 @@ int run_gather(const HybridPlan& p, const DeviceTables& dt, const float2* q, cha
     (void)dt;
 #define PL_G(KB, RSC) \
     if (p.block == KB && p.window_pad == RSC) return launch_gather<KB, RSC>(a, smem, blocks, s, q, tab, G);
-    PL_G(64, 12) PL_G(64, 16) PL_G(64, 20) PL_G(64, 24) PL_G(64, 33)
-    PL_G(32, 12) PL_G(32, 16) PL_G(32, 20) PL_G(32, 24) PL_G(32, 33)
+    PL_GATHER_CLASSES(PL_G)
 #undef PL_G
     return fail(PL_EUNSUPPORTED, "no pixel-per-lane back-projection for %d-chunk rows", p.window_pad);
 }
@@ -865,8 +879,7 @@ int launch_gather_batch(const void* descs, const void* items, const int* bounds,
                            s, args_descs, args_items, bounds, counters, ws);                                    \
         return check_launch("batched back-projection");                                                         \
     }
-    PL_GB(64, 12) PL_GB(64, 16) PL_GB(64, 20) PL_GB(64, 24) PL_GB(64, 33)
-    PL_GB(32, 12) PL_GB(32, 16) PL_GB(32, 20) PL_GB(32, 24) PL_GB(32, 33)
+    PL_GATHER_CLASSES(PL_GB)
 #undef PL_GB
     return fail(PL_EUNSUPPORTED, "no batched back-projection for %d k_z bins, %d-chunk rows", kb, rsc);
 }
@@ -903,7 +916,7 @@ int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, cons
 }
 
 size_t backproject_gather_lds_bytes(int rows, int row_chunks) {
-    return 2ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
+    return 1ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
 }
 
 size_t gather_table_bytes(const HybridPlan& p) {

@@ -187,8 +187,9 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         return fail(PL_EUNSUPPORTED, "the MFMA back-projection does not fit this grid");
     // VALU back-projection: the pixel-per-lane kernel when its 8x8 tile's
     // window fits (32 k_z bins per workgroup by default: the narrower k'
-    // band of a smaller block coarsens the range grid, and four workgroups
-    // fit a CU), else one k_z bin per lane (one bin per lane by default:
+    // band of a smaller block coarsens the range grid, and with 64 bins the
+    // row buffers halve the workgroups per CU), else one k_z bin per lane
+    // (one bin per lane by default:
     // more bins per lane make the staged window too large for several
     // resident workgroups per CU).
     p.bp_gather = false;
@@ -205,7 +206,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
             set_blocks(p.force_kb ? p.force_kb : 32, p.sigma_l);
             const double rt = 0.5 * std::hypot(7.0 * grid->dx, 7.0 * grid->dy);
             const int nchk = (static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7 + 1) / 2;  // 2-sample chunks
-            const int rows[5] = {12, 16, 20, 24, 33};
+            const int rows[6] = {12, 14, 18, 24, 32, 40};   // compiled row classes
             int rsc = 0;
             for (int r : rows)
                 if (!rsc && nchk + 1 <= r) rsc = r;
