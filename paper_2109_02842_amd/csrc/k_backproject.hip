@@ -294,8 +294,14 @@ struct BatchScanDesc {
 constexpr int kGatherWaves = 4;   // wavefronts per workgroup
 constexpr int kGatherBatch = 4;   // channels per weight batch
 
-// RSC 16-byte chunks per LDS row, of which nchk are staged: the window's
-// chunks and one more, since a pixel may read one chunk past its last tap.
+// RSC 16-byte chunks per LDS row, of which nchk (the window) are staged.
+// With A, B = (l_c -+ reach - l_lo) / du for the tile centre's range l_c,
+// every pixel has u in [A, B]; the window starts at s in
+// [floor(A) - 3, floor(A) - 2] (even), so a first tap f = floor(u) - 1 has
+// f - s in [1, ceil(B - A) + 2], at most the window length minus 6 (the
+// planner's window is ceil(2 reach / du) + 8 samples or more: the bound
+// plus one sample against float rounding).  A pixel reads the aligned
+// samples [(f - s) & ~1, + 5), inside the window while f - s <= wpl - 5.
 // One (k_z block, tile) work item; tab = the scan's tile table; smem = the
 // workgroup's LDS (the weight slots, then the two row buffers).
 template <int KB, int RSC>
@@ -364,8 +370,9 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             const float uu = e.uf + dl * inv_du_f;
             const float fv = floorf(uu);
             const float t = uu - fv;
-            // the last chunk a pixel may read (past its taps) is staged too
-            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 6));
+            // within the window by the bound above; the clamp keeps every read
+            // inside the staged row whatever the rounding
+            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 5));
             const bool odd = i0 & 1;
             float v[4];
 #pragma unroll
@@ -773,7 +780,7 @@ BpgArgs gather_args(const HybridPlan& p) {
     a.n_tiles = p.tiles_x * p.tiles_y;
     a.n_work = a.n_tiles * p.n_blocks;
     a.per_xcd = (a.n_work + 7) / 8;
-    a.nchk = p.window / 2 + 1;  // staged chunks: the window and one more
+    a.nchk = p.window / 2;  // staged chunks: the window
     a.mono = p.mode == PL_MONO;
     a.x0 = p.x0;
     a.y0 = p.y0;
@@ -788,7 +795,7 @@ BpgArgs gather_args(const HybridPlan& p) {
 }
 
 int check_gather_plan(const HybridPlan& p, int rsc) {
-    const int nchk = p.window / 2 + 1;
+    const int nchk = p.window / 2;
     if (!p.bp_gather || (p.block != 32 && p.block != 64) || p.tile_x != 8 || p.tile_y != 8 || p.window % 2 ||
         nchk < 3 || nchk > p.window_pad || p.window_pad > rsc || 2 * nchk > p.n_l || p.waves != kGatherWaves)
         return fail(PL_EUNSUPPORTED, "pixel-per-lane back-projection: window %d, block %d", p.window, p.block);

@@ -201,15 +201,17 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         if (p.force_kpl == 0 && (p.force_tile == 0 || p.force_tile == 8) &&
             (p.force_waves == 0 || p.force_waves == 4)) {
             // staged rows start on an even sample (16-byte copies) and hold
-            // the window plus one chunk (a pixel reads three aligned chunks
-            // around its four taps)
+            // the window: the taps of every pixel of the 8x8 tile and the
+            // sample after them (a pixel reads three aligned chunks around
+            // its four taps), ceil(2 reach / du) + 7 samples with reach = 2 rt,
+            // and one more against float rounding
             set_blocks(p.force_kb ? p.force_kb : 32, p.sigma_l);
             const double rt = 0.5 * std::hypot(7.0 * grid->dx, 7.0 * grid->dy);
-            const int nchk = (static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7 + 1) / 2;  // 2-sample chunks
+            const int nchk = (static_cast<int>(std::ceil(4.0 * rt / p.du)) + 8 + 1) / 2;  // 2-sample chunks
             const int rows[6] = {12, 14, 18, 24, 32, 40};   // compiled row classes
             int rsc = 0;
             for (int r : rows)
-                if (!rsc && nchk + 1 <= r) rsc = r;
+                if (!rsc && nchk <= r) rsc = r;
             if (rsc && backproject_gather_lds_bytes(p.block, rsc) <= kMaxLds) {
                 p.bp_gather = true;
                 p.tile_x = p.tile_y = 8;

@@ -219,6 +219,59 @@ def test_valu_backprojection_plan_rules():
     assert p1.bp_kernel == "kz-lanes" and p1.tile == (4, 4)
 
 
+def _gather_window_margins(wl):
+    """Tap margins of the pixel-per-lane back-projection's staged window.
+
+    Replays, in float64, where the planner and the tile table put a tile's
+    window (start s: the tile centre's range minus its reach, two samples
+    lower, clamped to the range grid, even; length: the plan's window) and
+    returns the smallest distance of any pixel's range position u (in
+    samples from s) to the two limits that keep its reads inside the
+    window: u >= 1 (first tap floor(u) - 1 >= 0) and u < window - 3 (first
+    tap at most window - 5, whose aligned five-sample read ends inside).
+    The range grid starts at each channel's lowest range over the pixel
+    rectangle minus two samples.
+    """
+    g = pr.make_geometry(wl.array)
+    info = pr.hybrid_plan_info(g, wl.grid)
+    assert info.bp_kernel == "pixel-lanes"
+    gi = pr.geometry_info(g)
+    tx, rx = np.asarray(gi["tx"]).reshape(-1, 2), np.asarray(gi["rx"]).reshape(-1, 2)
+    gr = wl.grid
+    du, n_l, wpl = info.du, info.n_l, info.window
+    reach = math.hypot(7 * gr.dx, 7 * gr.dy)
+    X = gr.x0 + np.arange(gr.nx) * gr.dx
+    Y = gr.y0 + np.arange(gr.ny) * gr.dy
+    tiles_x, tiles_y = (gr.nx + 7) // 8, (gr.ny + 7) // 8
+    cx = gr.x0 + (np.arange(tiles_x) * 8 + 3.5) * gr.dx
+    cy = gr.y0 + (np.arange(tiles_y) * 8 + 3.5) * gr.dy
+    lo, hi = np.inf, np.inf
+    for c in range(tx.shape[0]):
+        def rng(px, py):
+            return (np.hypot(px[None, :] - tx[c, 0], py[:, None] - tx[c, 1]) +
+                    np.hypot(px[None, :] - rx[c, 0], py[:, None] - rx[c, 1]))
+        def to_rect(p):
+            return math.hypot(p[0] - min(max(p[0], X[0]), X[-1]), p[1] - min(max(p[1], Y[0]), Y[-1]))
+        llo = to_rect(tx[c]) + to_rect(rx[c]) - 2 * du
+        s = np.floor((rng(cx, cy) - reach - llo) / du).astype(np.int64) - 2
+        s = np.clip(s, 0, n_l - wpl) & ~1
+        s_pix = np.repeat(np.repeat(s, 8, axis=0), 8, axis=1)[: gr.ny, : gr.nx]
+        u = (rng(X, Y) - llo) / du - s_pix
+        lo = min(lo, float((u - 1).min()))
+        hi = min(hi, float(((wpl - 3) - u).min()))
+    return lo, hi
+
+
+@pytest.mark.parametrize("which", ["C1", "C2", "C3", "C5"])
+def test_gather_window_holds_every_tap(which):
+    """Every pixel's taps (and the aligned read past them) lie inside the
+    staged window with room to spare for float32 rounding of the range."""
+    wls = W.batch_c5() if which == "C5" else [getattr(W, which)]
+    for wl in wls:
+        lo, hi = _gather_window_margins(wl)
+        assert lo >= 0.5 and hi >= 0.5, (wl.name, lo, hi)
+
+
 def test_resample_range_method_plan_rules():
     g = pr.make_geometry(W.C2.array)
     base = pr.hybrid_plan_info(g, W.C2.grid)
