@@ -212,6 +212,272 @@ __global__ __launch_bounds__(256) void resample_kernel(const float2* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront-per-pair form for fine grids of N = 64 R points (R 2,3,5-smooth,
+// at most 32): one wavefront owns one (channel, k_z) pair and its LDS, so
+// the kernel has no workgroup barriers.  The inverse FFT splits N = 64 R:
+// with n = 64 a + l and k = k1 + R k2,
+//   X[k1 + R k2] = sum_l w64^(l k2) [wN^(l k1) sum_a x[64 a + l] wR^(a k1)],
+// (w_M = exp(+2 pi i / M)): lane l takes the R-point DFT over a in
+// registers and its twiddles, then the 15 (R) transforms of 64 points over
+// l run as two radix-8 passes through LDS (l = l1 + 8 l2, k2 = m1 + 8 m2).
+// Rows of the transposed stages are 72 complex values apart and the middle
+// stage writes its outputs at 9 m1 + l1 in the row, which keeps the 8-byte
+// LDS accesses of 32 lanes on distinct banks in every pass.
+
+// exp(+2 pi i j / R) at compile time (angle reduced to [-pi, pi], Taylor
+// series in double).
+constexpr double ct_angle(int j, int r) {
+    int m = j % r;
+    if (m < 0) m += r;
+    if (2 * m > r) m -= r;
+    return 2.0 * kPi * m / r;
+}
+constexpr double ct_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 16; ++n) {
+        term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ct_sin(double x) {
+    double term = x, sum = x;
+    for (int n = 1; n < 16; ++n) {
+        term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+template <int R>
+struct RootsOfUnity {
+    float re[R], im[R];
+    constexpr RootsOfUnity() : re(), im() {
+        for (int j = 0; j < R; ++j) {
+            re[j] = static_cast<float>(ct_cos(ct_angle(j, R)));
+            im[j] = static_cast<float>(ct_sin(ct_angle(j, R)));
+        }
+    }
+};
+
+// the factor a composite R is split by (the first of 8, 4, 2, 3, 5 below R)
+constexpr int split_factor(int r) {
+    return (r % 8 == 0 && r > 8) ? 8 : (r % 4 == 0 && r > 4) ? 4 : (r % 2 == 0 && r > 2) ? 2 : (r % 3 == 0 && r > 3) ? 3 : 5;
+}
+constexpr bool is_codelet(int r) { return r == 2 || r == 3 || r == 4 || r == 5 || r == 8; }
+
+// Inverse DFT of R values in registers, natural order in and out.
+template <int R>
+__device__ __forceinline__ void idft_reg(float2* x) {
+    if constexpr (is_codelet(R)) {
+        dft_small<R>(x, +1);
+    } else {
+        constexpr int A = split_factor(R), B = R / A;
+        constexpr RootsOfUnity<R> w{};
+        float2 t[R];
+        // n = n1 + A n2, k = B k1 + k2: B-point DFTs over n2, twiddles
+        // wR^(n1 k2), A-point DFTs over n1
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) {
+            float2 u[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) u[n2] = x[n1 + A * n2];
+            idft_reg<B>(u);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2)
+                t[n1 * B + k2] = (n1 * k2) % R == 0
+                                     ? u[k2]
+                                     : cmul(u[k2], make_float2(w.re[(n1 * k2) % R], w.im[(n1 * k2) % R]));
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            float2 v[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) v[n1] = t[n1 * B + k2];
+            idft_reg<A>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) x[B * k1 + k2] = v[k1];
+        }
+    }
+}
+
+// Orders this wavefront's LDS accesses: DS instructions of a wavefront
+// complete in issue order, so a compiler barrier suffices.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWaveRow = 72;   // complex values per row of the transposed stages
+
+struct NufftWaveArgs {
+    int n_z, n_f, n_l, n_pairs;
+    double du, h, beta, inv_h;
+};
+
+// LDS of one wavefront: n_f positions (double), n_f strengths, R rows.
+constexpr size_t nufft_wave_lds(int r, int n_f) { return 16ull * n_f + 8ull * r * kWaveRow; }
+
+// One workgroup (one wavefront) per (channel c, k_z bin kap); the same
+// strengths, spreading and deapodisation as nufft_kernel.
+template <int R>
+__global__ __launch_bounds__(64) void nufft_wave_kernel(const float2* __restrict__ spec,
+                                                       const double* __restrict__ llo,
+                                                       const double* __restrict__ kp,
+                                                       const float* __restrict__ wk,
+                                                       const float2* __restrict__ tw,
+                                                       const float* __restrict__ deap, NufftWaveArgs a,
+                                                       float2* __restrict__ q) {
+    constexpr int N = 64 * R;
+    extern __shared__ double smem_d[];
+    double* py = smem_d;                                  // n_f fine-grid positions
+    float2* pa = reinterpret_cast<float2*>(py + a.n_f);   // n_f strengths
+    float2* A = pa + a.n_f;                               // R rows of kWaveRow
+    const int lane = threadIdx.x;
+    const int pair = blockIdx.x;                          // = c * n_z + kap
+    const int c = pair / a.n_z;
+    const int kap = pair - c * a.n_z;
+    const double lmid = llo[c] + (a.n_l / 2) * a.du;
+    const double cell = a.du * N * (0.5 / kPi);
+
+    // strengths and positions; first propagating frequency by ballot
+    int f0 = a.n_f;
+    for (int fb = 0; fb < a.n_f; fb += 64) {
+        const int f = fb + lane;
+        float w = 0.f;
+        if (f < a.n_f) {
+            const double kpf = kp[static_cast<size_t>(kap) * a.n_f + f];
+            w = wk[static_cast<size_t>(kap) * a.n_f + f];
+            const float2 sv = spec[static_cast<size_t>(pair) * a.n_f + f];
+            pa[f] = cscale(cmul(sv, cis(kpf * lmid)), w);
+            py[f] = kpf * cell;
+        }
+        const unsigned long long m = __ballot(w != 0.0f);
+        if (f0 == a.n_f && m) f0 = fb + __ffsll(static_cast<long long>(m)) - 1;
+    }
+    float2* qo = q + static_cast<size_t>(pair) * a.n_l;
+    if (f0 >= a.n_f) {  // nothing propagates at this k_z
+        for (int i = lane; i < a.n_l; i += 64) qo[i] = make_float2(0.f, 0.f);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) A[64 * j + lane] = make_float2(0.f, 0.f);
+    wave_lds_sync();
+
+    // spreading onto the fine grid: each cell gathers its neighbours (the
+    // positions rise with f) found by binary search
+    const int klo = static_cast<int>(floor(py[f0] - a.h)) + 1;
+    const int khi = static_cast<int>(floor(py[a.n_f - 1] + a.h));
+    const int ncell = min(khi - klo + 1, N);
+    for (int ci = lane; ci < ncell; ci += 64) {
+        const int k = klo + ci;
+        const double left = k - a.h;
+        int lo = f0, hi = a.n_f;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (py[mid] > left) hi = mid;
+            else lo = mid + 1;
+        }
+        float2 acc = make_float2(0.f, 0.f);
+        for (int f = lo; f < a.n_f; ++f) {
+            const double d = k - py[f];
+            if (d <= -a.h) break;
+            const float z = static_cast<float>(d * a.inv_h);
+            const float phi = __expf(static_cast<float>(a.beta) * (__builtin_amdgcn_sqrtf(fmaxf(1.f - z * z, 0.f)) - 1.f));
+            acc.x += pa[f].x * phi;
+            acc.y += pa[f].y * phi;
+        }
+        // every cell index is within one period of [0, N) (see nufft_kernel)
+        A[k < 0 ? k + N : (k >= N ? k - N : k)] = acc;
+    }
+    wave_lds_sync();
+
+    // R-point transforms over a, twiddles wN^(l k1), rows k1
+    {
+        float2 x[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[j] = A[64 * j + lane];
+        idft_reg<R>(x);
+#pragma unroll
+        for (int k1 = 1; k1 < R; ++k1) {
+            const float2 w = tw[lane * k1];   // exp(-2 pi i lane k1 / N), lane k1 < N
+            x[k1] = cmul(x[k1], make_float2(w.x, -w.y));
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) A[k1 * kWaveRow + lane] = x[k1];
+    }
+    wave_lds_sync();
+
+    // first radix-8 pass over l2 (butterfly (k1, l1)), twiddles w64^(l1 m1)
+    for (int b = lane; b < 8 * R; b += 64) {
+        const int k1 = b >> 3, l1 = b & 7;
+        float2* row = A + k1 * kWaveRow;
+        float2 u[8];
+#pragma unroll
+        for (int l2 = 0; l2 < 8; ++l2) u[l2] = row[l1 + 8 * l2];
+        dft_small<8>(u, +1);
+#pragma unroll
+        for (int m1 = 1; m1 < 8; ++m1) {
+            const float2 w = tw[R * l1 * m1];
+            u[m1] = cmul(u[m1], make_float2(w.x, -w.y));
+        }
+#pragma unroll
+        for (int m1 = 0; m1 < 8; ++m1) row[9 * m1 + l1] = u[m1];
+    }
+    wave_lds_sync();
+
+    // second radix-8 pass over l1 (butterfly (k1, m1)): X[k1 + R (m1 + 8 m2)],
+    // deapodised into q[i] for k = (i - n_l / 2) mod N
+    const int half = a.n_l / 2;
+    for (int b = lane; b < 8 * R; b += 64) {
+        const int k1 = b >> 3, m1 = b & 7;
+        const float2* row = A + k1 * kWaveRow + 9 * m1;
+        float2 v[8];
+#pragma unroll
+        for (int l1 = 0; l1 < 8; ++l1) v[l1] = row[l1];
+        dft_small<8>(v, +1);
+#pragma unroll
+        for (int m2 = 0; m2 < 8; ++m2) {
+            const int k = k1 + R * (m1 + 8 * m2);
+            const int i = k < half ? k + half : k - N + half;
+            if (i >= 0 && i < a.n_l) qo[i] = cscale(v[m2], deap[i]);
+        }
+    }
+}
+
+template <int R>
+int launch_nufft_wave(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
+    NufftWaveArgs a{};
+    a.n_z = p.n_z;
+    a.n_f = p.n_f;
+    a.n_l = p.n_l;
+    const long long pairs = static_cast<long long>(p.n_ch) * p.n_z;
+    if (pairs > 0x7fffffffLL) return fail(PL_EUNSUPPORTED, "too many (channel, k_z) pairs");
+    a.n_pairs = static_cast<int>(pairs);
+    a.du = p.du;
+    a.h = p.h;
+    a.inv_h = 1.0 / p.h;
+    a.beta = p.beta;
+    const size_t smem = nufft_wave_lds(R, p.n_f);
+    auto fn = nufft_wave_kernel<R>;
+    if (smem > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+        if (e != hipSuccess) return fail(PL_EDEVICE, "range compression LDS of %zu bytes: %s", smem, hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(pairs)), dim3(64), smem, s, spec,
+                       reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<const double*>(ws + p.off_kp),
+                       reinterpret_cast<const float*>(ws + p.off_wk), reinterpret_cast<const float2*>(ws + p.off_tw_fine),
+                       reinterpret_cast<const float*>(ws + p.off_deap), a, q);
+    return check_launch("range compression (wavefront per pair)");
+}
+
+// Fine-grid sizes with a wavefront-per-pair kernel: N = 64 R.
+#define PL_NUFFT_WAVE_SIZES(X) \
+    X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32)
+
 }  // namespace
 
 size_t nufft_smem_bytes(const HybridPlan& p) {
@@ -232,6 +498,12 @@ int launch_range_compress_fp32(const HybridPlan& p, const float2* spec, char* ws
     a.inv_h = 1.0 / p.h;
     a.beta = p.beta;
     a.rad = p.fine_rad;
+    if (p.n_fine % 64 == 0) {
+#define PL_NW(R) \
+        if (p.n_fine == 64 * R) return launch_nufft_wave<R>(p, spec, ws, q, s);
+        PL_NUFFT_WAVE_SIZES(PL_NW)
+#undef PL_NW
+    }
     const size_t smem = nufft_smem_bytes(p);
     if (smem > 65536) return fail(PL_EUNSUPPORTED, "range compression needs %zu bytes of LDS", smem);
     const long long blocks = static_cast<long long>(p.n_ch) * p.n_z;
