@@ -311,6 +311,58 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kWaveRow = 72;   // complex values per row of the transposed stages
 
+// Inverse FFT of the N = 64 R values A[0, N) of one wavefront (see above);
+// out(k, X[k]) receives every output once.  A is R rows of kWaveRow.
+template <int R, typename Out>
+__device__ __forceinline__ void wave_ifft(float2* A, const float2* __restrict__ tw, int lane, Out out) {
+    // R-point transforms over a, twiddles wN^(l k1), rows k1
+    {
+        float2 x[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[j] = A[64 * j + lane];
+        idft_reg<R>(x);
+#pragma unroll
+        for (int k1 = 1; k1 < R; ++k1) {
+            const float2 w = tw[lane * k1];   // exp(-2 pi i lane k1 / N), lane k1 < N
+            x[k1] = cmul(x[k1], make_float2(w.x, -w.y));
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) A[k1 * kWaveRow + lane] = x[k1];
+    }
+    wave_lds_sync();
+
+    // first radix-8 pass over l2 (butterfly (k1, l1)), twiddles w64^(l1 m1)
+    for (int b = lane; b < 8 * R; b += 64) {
+        const int k1 = b >> 3, l1 = b & 7;
+        float2* row = A + k1 * kWaveRow;
+        float2 u[8];
+#pragma unroll
+        for (int l2 = 0; l2 < 8; ++l2) u[l2] = row[l1 + 8 * l2];
+        dft_small<8>(u, +1);
+#pragma unroll
+        for (int m1 = 1; m1 < 8; ++m1) {
+            const float2 w = tw[R * l1 * m1];
+            u[m1] = cmul(u[m1], make_float2(w.x, -w.y));
+        }
+#pragma unroll
+        for (int m1 = 0; m1 < 8; ++m1) row[9 * m1 + l1] = u[m1];
+    }
+    wave_lds_sync();
+
+    // second radix-8 pass over l1 (butterfly (k1, m1)): X[k1 + R (m1 + 8 m2)]
+    for (int b = lane; b < 8 * R; b += 64) {
+        const int k1 = b >> 3, m1 = b & 7;
+        const float2* row = A + k1 * kWaveRow + 9 * m1;
+        float2 v[8];
+#pragma unroll
+        for (int l1 = 0; l1 < 8; ++l1) v[l1] = row[l1];
+        dft_small<8>(v, +1);
+#pragma unroll
+        for (int m2 = 0; m2 < 8; ++m2) out(k1 + R * (m1 + 8 * m2), v[m2]);
+    }
+}
+
 struct NufftWaveArgs {
     int n_z, n_f, n_l, n_pairs;
     double du, h, beta, inv_h;
@@ -393,58 +445,13 @@ __global__ __launch_bounds__(64) void nufft_wave_kernel(const float2* __restrict
     }
     wave_lds_sync();
 
-    // R-point transforms over a, twiddles wN^(l k1), rows k1
-    {
-        float2 x[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) x[j] = A[64 * j + lane];
-        idft_reg<R>(x);
-#pragma unroll
-        for (int k1 = 1; k1 < R; ++k1) {
-            const float2 w = tw[lane * k1];   // exp(-2 pi i lane k1 / N), lane k1 < N
-            x[k1] = cmul(x[k1], make_float2(w.x, -w.y));
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int k1 = 0; k1 < R; ++k1) A[k1 * kWaveRow + lane] = x[k1];
-    }
-    wave_lds_sync();
-
-    // first radix-8 pass over l2 (butterfly (k1, l1)), twiddles w64^(l1 m1)
-    for (int b = lane; b < 8 * R; b += 64) {
-        const int k1 = b >> 3, l1 = b & 7;
-        float2* row = A + k1 * kWaveRow;
-        float2 u[8];
-#pragma unroll
-        for (int l2 = 0; l2 < 8; ++l2) u[l2] = row[l1 + 8 * l2];
-        dft_small<8>(u, +1);
-#pragma unroll
-        for (int m1 = 1; m1 < 8; ++m1) {
-            const float2 w = tw[R * l1 * m1];
-            u[m1] = cmul(u[m1], make_float2(w.x, -w.y));
-        }
-#pragma unroll
-        for (int m1 = 0; m1 < 8; ++m1) row[9 * m1 + l1] = u[m1];
-    }
-    wave_lds_sync();
-
-    // second radix-8 pass over l1 (butterfly (k1, m1)): X[k1 + R (m1 + 8 m2)],
-    // deapodised into q[i] for k = (i - n_l / 2) mod N
     const int half = a.n_l / 2;
-    for (int b = lane; b < 8 * R; b += 64) {
-        const int k1 = b >> 3, m1 = b & 7;
-        const float2* row = A + k1 * kWaveRow + 9 * m1;
-        float2 v[8];
-#pragma unroll
-        for (int l1 = 0; l1 < 8; ++l1) v[l1] = row[l1];
-        dft_small<8>(v, +1);
-#pragma unroll
-        for (int m2 = 0; m2 < 8; ++m2) {
-            const int k = k1 + R * (m1 + 8 * m2);
-            const int i = k < half ? k + half : k - N + half;
-            if (i >= 0 && i < a.n_l) qo[i] = cscale(v[m2], deap[i]);
-        }
-    }
+    const float* dp = deap;
+    wave_ifft<R>(A, tw, lane, [&](int k, float2 v) {
+        // deapodised into q[i] for k = (i - n_l / 2) mod N
+        const int i = k < half ? k + half : k - N + half;
+        if (i >= 0 && i < a.n_l) qo[i] = cscale(v, dp[i]);
+    });
 }
 
 template <int R>
@@ -472,6 +479,108 @@ int launch_nufft_wave(const HybridPlan& p, const float2* spec, char* ws, float2*
                        reinterpret_cast<const float*>(ws + p.off_wk), reinterpret_cast<const float2*>(ws + p.off_tw_fine),
                        reinterpret_cast<const float*>(ws + p.off_deap), a, q);
     return check_launch("range compression (wavefront per pair)");
+}
+
+// Wavefront-per-pair form of resample_kernel for fine grids of N = 64 R
+// points (the same uniform-grid samples; the FFT of nufft_wave_kernel).
+template <int R>
+__global__ __launch_bounds__(64) void resample_wave_kernel(const float2* __restrict__ spec,
+                                                          const double* __restrict__ llo,
+                                                          const double* __restrict__ lref,
+                                                          const double* __restrict__ kp,
+                                                          const float* __restrict__ wk,
+                                                          const float2* __restrict__ tw, ResampleArgs a,
+                                                          float2* __restrict__ q) {
+    constexpr int N = 64 * R;
+    extern __shared__ double smem_d[];
+    float2* pa = reinterpret_cast<float2*>(smem_d);   // n_f demodulated samples
+    float2* A = pa + a.n_f;                           // R rows of kWaveRow
+    const int lane = threadIdx.x;
+    const int pair = blockIdx.x;                      // = c * n_z + kap
+    const int c = pair / a.n_z;
+    const int kap = pair - c * a.n_z;
+    const double lmid = llo[c] + (a.n_l / 2) * a.du;
+    const double lr = lref[c];
+    const double kr0 = a.kref[kap / a.block];
+    const double* kprow = kp + static_cast<size_t>(kap) * a.n_f;
+
+    int f0 = a.n_f;
+    for (int fb = 0; fb < a.n_f; fb += 64) {
+        const int f = fb + lane;
+        float w = 0.f;
+        if (f < a.n_f) {
+            const float2 sv = spec[static_cast<size_t>(pair) * a.n_f + f];
+            pa[f] = cmul(sv, cis(kprow[f] * lr));
+            w = wk[static_cast<size_t>(kap) * a.n_f + f];
+        }
+        const unsigned long long m = __ballot(w != 0.0f);
+        if (f0 == a.n_f && m) f0 = fb + __ffsll(static_cast<long long>(m)) - 1;
+    }
+    float2* qo = q + static_cast<size_t>(pair) * a.n_l;
+    if (f0 >= a.n_f) {  // nothing propagates at this k_z
+        for (int i = lane; i < a.n_l; i += 64) qo[i] = make_float2(0.f, 0.f);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) A[64 * j + lane] = make_float2(0.f, 0.f);
+    wave_lds_sync();
+
+    const int sk = kap < (a.n_z + 1) / 2 ? kap : kap - a.n_z;
+    const double kz = 2.0 * kPi * sk / (a.n_z * a.scan_step);
+    const double kz2q = 0.25 * kz * kz;
+    const long long m_lo = static_cast<long long>(ceil((kprow[f0] + kr0) / a.dkl - 1e-9));
+    const long long m_hi = static_cast<long long>(floor((kprow[a.n_f - 1] + kr0) / a.dkl + 1e-9));
+    const long long m0 = llround(kr0 / a.dkl);
+    const int n_pts = min(4, a.n_f - f0);
+    const double dl = lmid - lr;
+    const float wscale = static_cast<float>(a.dkl * a.inv_dk);
+    for (long long m = m_lo + lane; m <= m_hi; m += 64) {
+        const double kl = static_cast<double>(m) * a.dkl;
+        const double t = (sqrt(kl * kl + kz2q) - a.k0) * a.inv_dk;
+        const int st = min(max(static_cast<int>(floor(t)) - 1, f0), a.n_f - n_pts);
+        const float x = static_cast<float>(t - st);   // nodes at 0 .. n_pts-1
+        float w[4];
+        if (n_pts == 4) {
+            const float a0 = x, a1 = x - 1.f, a2 = x - 2.f, a3 = x - 3.f;
+            w[0] = -(1.f / 6.f) * a1 * a2 * a3;
+            w[1] = 0.5f * a0 * a2 * a3;
+            w[2] = -0.5f * a0 * a1 * a3;
+            w[3] = (1.f / 6.f) * a0 * a1 * a2;
+        } else {  // 1-3 propagating samples: all of them
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float wj = j < n_pts ? 1.f : 0.f;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (i != j && i < n_pts) wj *= (x - i) / static_cast<float>(j - i);
+                w[j] = wj;
+            }
+        }
+        float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float2 pj = pa[min(st + j, a.n_f - 1)];
+            v.x += w[j] * pj.x;
+            v.y += w[j] * pj.y;
+        }
+        const int n = static_cast<int>(m - m0);
+        const double kpm = n * a.dkl;
+        float scale = static_cast<float>(kl) * wscale;
+        if (a.bspline) {
+            const float y = static_cast<float>(0.5 * kpm * a.du), y2 = y * y;
+            const float sinc =
+                1.f + y2 * (-1.f / 6 + y2 * (1.f / 120 + y2 * (-1.f / 5040 + y2 * (1.f / 362880 - y2 * (1.f / 39916800)))));
+            scale /= (sinc * sinc) * (sinc * sinc);
+        }
+        A[n < 0 ? n + N : n] = cscale(cmul(v, cis(kpm * dl)), scale);
+    }
+    wave_lds_sync();
+
+    const int half = a.n_l / 2;
+    wave_ifft<R>(A, tw, lane, [&](int k, float2 v) {
+        const int i = k < half ? k + half : k - N + half;
+        if (i >= 0 && i < a.n_l) qo[i] = v;
+    });
 }
 
 // Fine-grid sizes with a wavefront-per-pair kernel: N = 64 R.
@@ -540,10 +649,29 @@ int launch_range_compress_resample(const HybridPlan& p, const float2* spec, char
         if (std::fabs(p.kref[b] / p.dkl - std::nearbyint(p.kref[b] / p.dkl)) > 1e-6)
             return fail(PL_EINVAL, "resampling range compression: reference wavenumber off the grid");
     a.rad = p.fine_rad;
-    const size_t smem = static_cast<size_t>(p.n_f + (p.n_f & 1)) * 8 + 2ull * p.n_fine * 8;
-    if (smem > 65536) return fail(PL_EUNSUPPORTED, "resampling range compression needs %zu bytes of LDS", smem);
     const long long blocks = static_cast<long long>(p.n_ch) * p.n_z;
     if (blocks > 0x7fffffffLL) return fail(PL_EUNSUPPORTED, "too many (channel, k_z) pairs");
+    if (p.n_fine % 64 == 0) {
+#define PL_RW(R)                                                                                                  \
+        if (p.n_fine == 64 * R) {                                                                                 \
+            const size_t smem_w = 8ull * p.n_f + 8ull * R * kWaveRow;                                             \
+            if (smem_w > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(resample_wave_kernel<R>),    \
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,                 \
+                                                      static_cast<int>(smem_w)) != hipSuccess)                    \
+                return fail(PL_EDEVICE, "resampling range compression: LDS of %zu bytes refused", smem_w);        \
+            hipLaunchKernelGGL(resample_wave_kernel<R>, dim3(static_cast<unsigned>(blocks)), dim3(64), smem_w, s,  \
+                               spec, reinterpret_cast<const double*>(ws + p.off_llo),                             \
+                               reinterpret_cast<const double*>(ws + p.off_lref),                                  \
+                               reinterpret_cast<const double*>(ws + p.off_kp),                                    \
+                               reinterpret_cast<const float*>(ws + p.off_wk),                                     \
+                               reinterpret_cast<const float2*>(ws + p.off_tw_fine), a, q);                        \
+            return check_launch("range compression (resampling, wavefront per pair)");                           \
+        }
+        PL_NUFFT_WAVE_SIZES(PL_RW)
+#undef PL_RW
+    }
+    const size_t smem = static_cast<size_t>(p.n_f + (p.n_f & 1)) * 8 + 2ull * p.n_fine * 8;
+    if (smem > 65536) return fail(PL_EUNSUPPORTED, "resampling range compression needs %zu bytes of LDS", smem);
     hipLaunchKernelGGL(resample_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, spec,
                        reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<const double*>(ws + p.off_lref),
                        reinterpret_cast<const double*>(ws + p.off_kp), reinterpret_cast<const float*>(ws + p.off_wk),

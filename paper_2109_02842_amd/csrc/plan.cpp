@@ -275,11 +275,22 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
 
     // range samples: a multiple of 4 (8-byte stores of split BF16 profiles)
-    // with a 2,3,5-smooth fine grid of 2 n_l
+    // with a 2,3,5-smooth fine grid of 2 n_l.  The FP32 range compressions
+    // have a wavefront-per-pair kernel for fine grids of 64 R points (R
+    // 2,3,5-smooth, at most 32), about twice as fast per point as the
+    // workgroup kernel: n_l = 32 R when that adds at most a quarter.
     int nl = static_cast<int>(std::ceil(span / p.du)) + 8;
     nl = std::max(nl, p.window + 2);
     nl = (nl + 3) & ~3;
+    const int nl_min = nl;
     while (!is_fft_friendly(2 * nl)) nl += 4;
+    if (p.precision == PL_PREC_FP32) {
+        for (int r = (nl_min + 31) / 32; r <= 32; ++r)
+            if (is_fft_friendly(r)) {
+                if (32 * r <= nl_min + nl_min / 4) nl = 32 * r;
+                break;
+            }
+    }
     p.n_l = nl;
     p.n_fine = 2 * nl;
     if (p.n_fine > kMaxFine)
