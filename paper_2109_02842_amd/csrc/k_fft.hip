@@ -95,8 +95,7 @@ __global__ void twiddle_kernel(float2* tw, int n) {
 struct FftArgs {
     int n, nbatch, inner, per_wg, ld, sign, n_fast_in, n_fast_out;
     long long in_so, in_si, in_sn, out_so, out_si, out_sn;
-    float scale;
-    int pad_;
+    float scale, inv_inner;
     Radices rad;
 };
 
@@ -144,6 +143,83 @@ __global__ __launch_bounds__(256) void fft_strided_kernel(const float2* __restri
     }
 }
 
+// The same batched strided FFT for N = 64 R (R at most 8) on the wavefront
+// FFT (wave_ifft): a workgroup stages TB transforms in LDS with loads and
+// stores that run along whichever of (transform, element) is contiguous in
+// memory (TB = 16: 128-byte runs across transforms), its four wavefronts
+// transform them in place (wave_ifft's last radix-8 pass is a single pass
+// for R <= 8, so every lane has read its inputs before any output lands),
+// and the forward direction conjugates on the way in and out.  Transforms
+// are kWaveRow R + 2 values apart in LDS: 4 dwords of bank offset apiece.
+template <int R, int TB>
+__global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __restrict__ in,
+                                                               float2* __restrict__ out,
+                                                               const float2* __restrict__ tw, FftArgs a) {
+    constexpr int N = 64 * R;
+    constexpr int PS = kWaveRow * R + 2;
+    extern __shared__ float2 smem[];
+    const int b0 = blockIdx.x * TB;
+    const int nb = min(TB, a.nbatch - b0);
+    const int tid = threadIdx.x;
+    const bool fwd = a.sign < 0;
+    for (int e = tid; e < TB * N; e += 256) {
+        int t, i;
+        if (a.n_fast_in) {
+            t = e / N;
+            i = e - t * N;
+        } else {
+            i = e / TB;
+            t = e - i * TB;
+        }
+        if (t < nb) {
+            const int b = b0 + t;
+            const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
+            float2 v = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+            if (fwd) v.y = -v.y;
+            smem[t * PS + i] = v;
+        }
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int t = wave; t < nb; t += 4) {
+        float2* A = smem + t * PS;
+        wave_ifft<R>(A, tw, lane, [&](int k, float2 v) { A[k] = v; });
+    }
+    __syncthreads();
+    for (int e = tid; e < TB * N; e += 256) {
+        int t, i;
+        if (a.n_fast_out) {
+            t = e / N;
+            i = e - t * N;
+        } else {
+            i = e / TB;
+            t = e - i * TB;
+        }
+        if (t < nb) {
+            const int b = b0 + t;
+            const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
+            float2 v = smem[t * PS + i];
+            if (fwd) v.y = -v.y;
+            out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(v, a.scale);
+        }
+    }
+}
+
+template <int R>
+int launch_fft_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, hipStream_t s,
+                    const char* what) {
+    constexpr int TB = 16;
+    const size_t smem = static_cast<size_t>(TB) * (kWaveRow * R + 2) * sizeof(float2);
+    auto fn = fft_wave_strided_kernel<R, TB>;
+    if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            static_cast<int>(smem)) != hipSuccess)
+        return fail(PL_EDEVICE, "%s: LDS of %zu bytes refused", what, smem);
+    const long long blocks = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out, tw, a);
+    return check_launch(what);
+}
+
 int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nbatch, int inner,
             long long in_so, long long in_si, long long in_sn, long long out_so, long long out_si,
             long long out_sn, int sign, float scale, const Radices& rad, hipStream_t s,
@@ -164,9 +240,23 @@ int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nb
     a.out_si = out_si;
     a.out_sn = out_sn;
     a.scale = scale;
+    a.inv_inner = 1.0f / inner;
     a.rad = rad;
     if (nbatch <= 0) return PL_OK;
     if (nbatch > (1LL << 31) - 1) return fail(PL_EUNSUPPORTED, "%s: too many transforms", what);
+    // the wavefront kernel splits batch indices with a float reciprocal (exact
+    // below 2^22)
+    if (n % 64 == 0 && nbatch + inner < (1LL << 21)) {
+        switch (n / 64) {
+            case 2: return launch_fft_wave<2>(a, in, out, tw, s, what);
+            case 3: return launch_fft_wave<3>(a, in, out, tw, s, what);
+            case 4: return launch_fft_wave<4>(a, in, out, tw, s, what);
+            case 5: return launch_fft_wave<5>(a, in, out, tw, s, what);
+            case 6: return launch_fft_wave<6>(a, in, out, tw, s, what);
+            case 8: return launch_fft_wave<8>(a, in, out, tw, s, what);
+            default: break;
+        }
+    }
     const size_t smem = 2ull * a.per_wg * a.ld * sizeof(float2);
     const long long blocks = (nbatch + a.per_wg - 1) / a.per_wg;
     hipLaunchKernelGGL(fft_strided_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out,

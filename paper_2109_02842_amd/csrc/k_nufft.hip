@@ -215,153 +215,7 @@ __global__ __launch_bounds__(256) void resample_kernel(const float2* __restrict_
 // ---------------------------------------------------------------------------
 // Wavefront-per-pair form for fine grids of N = 64 R points (R 2,3,5-smooth,
 // at most 32): one wavefront owns one (channel, k_z) pair and its LDS, so
-// the kernel has no workgroup barriers.  The inverse FFT splits N = 64 R:
-// with n = 64 a + l and k = k1 + R k2,
-//   X[k1 + R k2] = sum_l w64^(l k2) [wN^(l k1) sum_a x[64 a + l] wR^(a k1)],
-// (w_M = exp(+2 pi i / M)): lane l takes the R-point DFT over a in
-// registers and its twiddles, then the 15 (R) transforms of 64 points over
-// l run as two radix-8 passes through LDS (l = l1 + 8 l2, k2 = m1 + 8 m2).
-// Rows of the transposed stages are 72 complex values apart and the middle
-// stage writes its outputs at 9 m1 + l1 in the row, which keeps the 8-byte
-// LDS accesses of 32 lanes on distinct banks in every pass.
-
-// exp(+2 pi i j / R) at compile time (angle reduced to [-pi, pi], Taylor
-// series in double).
-constexpr double ct_angle(int j, int r) {
-    int m = j % r;
-    if (m < 0) m += r;
-    if (2 * m > r) m -= r;
-    return 2.0 * kPi * m / r;
-}
-constexpr double ct_cos(double x) {
-    double term = 1.0, sum = 1.0;
-    for (int n = 1; n < 16; ++n) {
-        term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
-        sum += term;
-    }
-    return sum;
-}
-constexpr double ct_sin(double x) {
-    double term = x, sum = x;
-    for (int n = 1; n < 16; ++n) {
-        term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
-        sum += term;
-    }
-    return sum;
-}
-template <int R>
-struct RootsOfUnity {
-    float re[R], im[R];
-    constexpr RootsOfUnity() : re(), im() {
-        for (int j = 0; j < R; ++j) {
-            re[j] = static_cast<float>(ct_cos(ct_angle(j, R)));
-            im[j] = static_cast<float>(ct_sin(ct_angle(j, R)));
-        }
-    }
-};
-
-// the factor a composite R is split by (the first of 8, 4, 2, 3, 5 below R)
-constexpr int split_factor(int r) {
-    return (r % 8 == 0 && r > 8) ? 8 : (r % 4 == 0 && r > 4) ? 4 : (r % 2 == 0 && r > 2) ? 2 : (r % 3 == 0 && r > 3) ? 3 : 5;
-}
-constexpr bool is_codelet(int r) { return r == 2 || r == 3 || r == 4 || r == 5 || r == 8; }
-
-// Inverse DFT of R values in registers, natural order in and out.
-template <int R>
-__device__ __forceinline__ void idft_reg(float2* x) {
-    if constexpr (is_codelet(R)) {
-        dft_small<R>(x, +1);
-    } else {
-        constexpr int A = split_factor(R), B = R / A;
-        constexpr RootsOfUnity<R> w{};
-        float2 t[R];
-        // n = n1 + A n2, k = B k1 + k2: B-point DFTs over n2, twiddles
-        // wR^(n1 k2), A-point DFTs over n1
-#pragma unroll
-        for (int n1 = 0; n1 < A; ++n1) {
-            float2 u[B];
-#pragma unroll
-            for (int n2 = 0; n2 < B; ++n2) u[n2] = x[n1 + A * n2];
-            idft_reg<B>(u);
-#pragma unroll
-            for (int k2 = 0; k2 < B; ++k2)
-                t[n1 * B + k2] = (n1 * k2) % R == 0
-                                     ? u[k2]
-                                     : cmul(u[k2], make_float2(w.re[(n1 * k2) % R], w.im[(n1 * k2) % R]));
-        }
-#pragma unroll
-        for (int k2 = 0; k2 < B; ++k2) {
-            float2 v[A];
-#pragma unroll
-            for (int n1 = 0; n1 < A; ++n1) v[n1] = t[n1 * B + k2];
-            idft_reg<A>(v);
-#pragma unroll
-            for (int k1 = 0; k1 < A; ++k1) x[B * k1 + k2] = v[k1];
-        }
-    }
-}
-
-// Orders this wavefront's LDS accesses: DS instructions of a wavefront
-// complete in issue order, so a compiler barrier suffices.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-constexpr int kWaveRow = 72;   // complex values per row of the transposed stages
-
-// Inverse FFT of the N = 64 R values A[0, N) of one wavefront (see above);
-// out(k, X[k]) receives every output once.  A is R rows of kWaveRow.
-template <int R, typename Out>
-__device__ __forceinline__ void wave_ifft(float2* A, const float2* __restrict__ tw, int lane, Out out) {
-    // R-point transforms over a, twiddles wN^(l k1), rows k1
-    {
-        float2 x[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) x[j] = A[64 * j + lane];
-        idft_reg<R>(x);
-#pragma unroll
-        for (int k1 = 1; k1 < R; ++k1) {
-            const float2 w = tw[lane * k1];   // exp(-2 pi i lane k1 / N), lane k1 < N
-            x[k1] = cmul(x[k1], make_float2(w.x, -w.y));
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int k1 = 0; k1 < R; ++k1) A[k1 * kWaveRow + lane] = x[k1];
-    }
-    wave_lds_sync();
-
-    // first radix-8 pass over l2 (butterfly (k1, l1)), twiddles w64^(l1 m1)
-    for (int b = lane; b < 8 * R; b += 64) {
-        const int k1 = b >> 3, l1 = b & 7;
-        float2* row = A + k1 * kWaveRow;
-        float2 u[8];
-#pragma unroll
-        for (int l2 = 0; l2 < 8; ++l2) u[l2] = row[l1 + 8 * l2];
-        dft_small<8>(u, +1);
-#pragma unroll
-        for (int m1 = 1; m1 < 8; ++m1) {
-            const float2 w = tw[R * l1 * m1];
-            u[m1] = cmul(u[m1], make_float2(w.x, -w.y));
-        }
-#pragma unroll
-        for (int m1 = 0; m1 < 8; ++m1) row[9 * m1 + l1] = u[m1];
-    }
-    wave_lds_sync();
-
-    // second radix-8 pass over l1 (butterfly (k1, m1)): X[k1 + R (m1 + 8 m2)]
-    for (int b = lane; b < 8 * R; b += 64) {
-        const int k1 = b >> 3, m1 = b & 7;
-        const float2* row = A + k1 * kWaveRow + 9 * m1;
-        float2 v[8];
-#pragma unroll
-        for (int l1 = 0; l1 < 8; ++l1) v[l1] = row[l1];
-        dft_small<8>(v, +1);
-#pragma unroll
-        for (int m2 = 0; m2 < 8; ++m2) out(k1 + R * (m1 + 8 * m2), v[m2]);
-    }
-}
+// the kernel has no workgroup barriers; the inverse FFT is wave_ifft.
 
 struct NufftWaveArgs {
     int n_z, n_f, n_l, n_pairs;
