@@ -81,8 +81,11 @@ def multi_small():
 
 
 # ------------------------------------------------------------------ FFTs
-@pytest.mark.parametrize("n_scan", [10, 24, 256, 512])
+@pytest.mark.parametrize("n_scan", [10, 24, 128, 192, 256, 320, 384, 512])
 def test_scan_fft_and_kz_ifft(n_scan):
+    # 64 R points (R = 2, 3, 4, 5, 6, 8) take the wavefront FFT, the others
+    # the Stockham stages; 9 frequencies and 15 pixels leave partial
+    # workgroups and transforms that straddle channels
     a = replace(W.tiny("mono").array, n_scan=n_scan, n_freq=9)
     g = pr.make_geometry(a)
     say("scan_fft", n_scan)
@@ -141,27 +144,41 @@ def _kprime(wl, plan, kap):
 
 
 @pytest.mark.parametrize("interp", ["lagrange4", "bspline4"])
-@pytest.mark.parametrize("wlname", ["tiny-mono", "multi-small", "C1"])
+@pytest.mark.parametrize("wlname", ["tiny-mono", "multi-small", "C1", "evanescent-small"])
 def test_range_compress_matches_direct_nudft(interp, wlname):
-    wl = {"tiny-mono": W.tiny("mono"), "multi-small": multi_small(), "C1": W.C1}[wlname]
+    # fine grids of 192 (tiny), 384 (C1) and 512 (evanescent) points take the
+    # wavefront-per-pair kernel, 432 (multi-small) the workgroup kernel; the
+    # evanescent case has rows with no and with 1-3 propagating frequencies
+    wl = {"tiny-mono": W.tiny("mono"), "multi-small": multi_small(), "C1": W.C1,
+          "evanescent-small": evanescent_small()}[wlname]
     g = pr.make_geometry(wl.array)
     plan = pr.hybrid_plan_info(g, wl.grid, interp=interp)
     s = W.random_echo(wl.array, 8)
-    say("range_compress", wlname, interp, plan.n_l)
+    say("range_compress", wlname, interp, plan.n_l, plan.n_fine)
     spec = pr.scan_fft(g, dev(s))
     q, llo = pr.range_compress(g, wl.grid, spec, interp=interp)
     q = host(q)
     S = ohyb.scan_spectrum(s)
-    for kap in sorted({0, 1, wl.array.n_scan // 2, wl.array.n_scan - 1}):
+    kaps = {0, 1, wl.array.n_scan // 2, wl.array.n_scan - 1}
+    if wlname == "evanescent-small":
+        kaps = set(range(wl.array.n_scan))
+    n_dead = 0
+    for kap in sorted(kaps):
         kp, valid, arr = _kprime(wl, plan, kap)
         w = arr.k * valid
         if interp == "bspline4":
             x = 0.5 * kp * plan.du                 # B-spline prefilter 1/sinc^4, closed form
             w = w / np.where(valid, np.sinc(x / np.pi) ** 4, 1.0)
         for c in sorted({0, arr.n_channels // 2, arr.n_channels - 1}):
+            if not valid.any():                    # nothing propagates: the row is zero
+                n_dead += 1
+                assert not np.any(q[c, kap]), (kap, c)
+                continue
             l = llo[c] + plan.du * np.arange(plan.n_l)
             ref = onudft.nudft(w * S[c, kap], kp, l)
             assert rel(q[c, kap], ref) < 2e-5, (kap, c)
+    if wlname == "evanescent-small":
+        assert n_dead > 0
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
