@@ -29,6 +29,33 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
 
 
+def stage_rooflines(plan, a, wl, geom, stage, args):
+    """Algorithmic HBM bytes (and, for the FP32 NUFFT, FLOP) of the other
+    stages over their event-timed durations: the FFTs move the cube in and
+    out once; range compression reads the spectrum and writes the profiles
+    (FLOP per (c, k_z) pair: 5 n log2 n + n_f W 14 + 2 n_l with n = n_fine)."""
+    n_pairs = geom.n_channels * a.n_scan
+    npix = wl.grid.nx * wl.grid.ny
+    out = {}
+
+    def hbm(name, nbytes):
+        t = stage[name] * 1e-3
+        gbs = nbytes / t / 1e9
+        out[name] = {"bound": "hbm", "bytes": nbytes, "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
+                     "frac": gbs / HBM_PEAK_GBS}
+
+    hbm("scan_fft", 2 * n_pairs * a.n_freq * 8)
+    hbm("range_compress", n_pairs * (a.n_freq + plan.n_l) * 8)
+    hbm("kz_ifft", 2 * npix * a.n_scan * 8)
+    if args.precision == "fp32" and args.range_method == "nufft":
+        n = plan.n_fine
+        flop = n_pairs * (5 * n * math.log2(n) + a.n_freq * plan.kernel_width * 14 + 2 * plan.n_l)
+        tf = flop / (stage["range_compress"] * 1e-3) / 1e12
+        out["range_compress"].update({"flop": flop, "achieved_tflops": tf, "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                                      "frac_alu": tf / FP32_VECTOR_PEAK_TFLOPS})
+    return out
+
+
 def measured_traffic(kernel: str, workload: str, precision: str, n_l: int):
     """HBM bytes per back-projection launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
@@ -302,6 +329,7 @@ def main() -> int:
                          traffic=measured_traffic(plan.bp_kernel, args.config, args.precision, plan.n_l),
                          kernel="backproject", flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
         "stages_ms": stage,
+        "stages_roofline": stage_rooflines(plan, a, wl, geom, stage, args),
         "plan_build_ms": first_ms,
     }
     if not args.no_parity:
