@@ -341,12 +341,14 @@ int reconstruct_hybrid_events(const pl_geometry* geom, const pl_image_grid* grid
 
 /*
  * Adjoint of the imaging operator: image_dev ([z][y][x] complex64) ->
- * echo_dev ([c][m][f] complex64), the exact conjugate transpose of the
- * linear map echo -> image that reconstruct_hybrid evaluates (with the range
- * compression's sum taken exactly instead of by NUFFT): the forward transform
+ * echo_dev ([c][m][f] complex64), the conjugate transpose of the linear map
+ * echo -> image that reconstruct_hybrid evaluates: the forward transform
  * over z with 1/n_z, the scatter form of the back-projection (eq. 8b/19b
  * transposed: each pixel's interpolation taps times the conjugate carrier),
- * the direct type-2 sum over the range grid (eq. 8a/19a transposed) and the
+ * the range compression transposed (eq. 8a/19a: for fine grids of 64 R
+ * points, R 2,3,5-smooth and at most 32, the exact transpose of the NUFFT
+ * the forward call runs; otherwise the direct type-2 sum over the range
+ * grid, the transpose of the sum the NUFFT approximates) and the
  * unnormalised inverse transform over k_z.  It serves as the echo model of
  * least-squares refinement (scene image -> echo).  FP32 plans with the
  * pixel-per-lane back-projection and the NUFFT range method only
