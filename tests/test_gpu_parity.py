@@ -181,6 +181,42 @@ def test_range_compress_matches_direct_nudft(interp, wlname):
         assert n_dead > 0
 
 
+def _oversampling_for_fine_grid(g, grid, n_fine):
+    """A range-grid oversampling whose plan has this fine-grid size."""
+    for sig in np.arange(4.0, 60.0, 0.25):
+        try:
+            plan = pr.hybrid_plan_info(g, grid, l_oversample=float(sig))
+        except RuntimeError:
+            continue
+        if plan.n_fine == n_fine:
+            return float(sig), plan
+    raise AssertionError(f"no oversampling gives a {n_fine}-point fine grid")
+
+
+@pytest.mark.parametrize("radix", [4, 5, 9, 10, 16, 18, 20, 25, 27, 30, 32, 36])
+def test_range_compress_every_wavefront_radix(radix):
+    # C1 at the oversampling that makes the fine grid 64 R points: every
+    # R-point register DFT the wavefront NUFFT is compiled for that the
+    # workloads do not reach (R = 36 is past them: the workgroup kernel)
+    wl = W.C1
+    g = pr.make_geometry(wl.array)
+    sig, plan = _oversampling_for_fine_grid(g, wl.grid, 64 * radix)
+    say("range_compress radix", radix, "l_oversample", sig, "n_l", plan.n_l)
+    s = W.random_echo(wl.array, 30 + radix)
+    spec = pr.scan_fft(g, dev(s))
+    q, llo = pr.range_compress(g, wl.grid, spec, l_oversample=sig)
+    q = host(q)
+    S = ohyb.scan_spectrum(s)
+    for kap in (0, 7, wl.array.n_scan - 1):
+        kp, valid, arr = _kprime(wl, plan, kap)
+        x = 0.5 * kp * plan.du
+        w = arr.k * valid / np.where(valid, np.sinc(x / np.pi) ** 4, 1.0)
+        for c in (0, arr.n_channels - 1):
+            l = llo[c] + plan.du * np.arange(plan.n_l)
+            ref = onudft.nudft(w * S[c, kap], kp, l)
+            assert rel(q[c, kap], ref) < 2e-5, (radix, kap, c)
+
+
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 @pytest.mark.parametrize("wlname", ["tiny-mono", "multi-small", "C1"])
 def test_mfma_range_compress_matches_direct_nudft(precision, wlname):
