@@ -195,7 +195,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the reconstruction is not sharded across GPUs in this build)", flush=True)
+              "(the reconstruction is not sharded across GPUs)", flush=True)
         return 2
 
     import torch
