@@ -98,7 +98,14 @@ int make_hybrid_batch(int32_t n, const pl_geometry* const* geoms, const pl_image
         // heaviest scans first (work per item ~ channels), scan order kept among equals
         std::stable_sort(order.begin(), order.end(),
                          [&](int i, int j) { return b->plans[i].n_ch > b->plans[j].n_ch; });
-        std::vector<int> items;
+        // Eight per-XCD queues: every scan's (k_z block, tile) items, in
+        // order, split into eight contiguous shares (all items of a scan
+        // cost the same), and queue x holds share x of each scan in turn.
+        // The XCDs then work through the scans together, each on a compact
+        // range of one scan's range profiles, as separate launches would;
+        // a queue spanning whole scans instead keeps up to eight scans'
+        // profiles live at once (measured 10 % slower at C5).
+        std::vector<std::vector<int>> per_xcd(8);
         for (int s : order) {
             const HybridPlan& p = b->plans[s];
             DeviceTables dt;
@@ -108,23 +115,23 @@ int make_hybrid_batch(int32_t n, const pl_geometry* const* geoms, const pl_image
             if (rc) return bail(rc);
             q.smem = std::max(q.smem, backproject_gather_lds_bytes(kb, rsc));
             const int n_tiles = p.tiles_x * p.tiles_y;
-            for (int blk = 0; blk < p.n_blocks; ++blk)
-                for (int t = 0; t < n_tiles; ++t) {
-                    items.push_back(s);
-                    items.push_back(blk);
-                    items.push_back(t);
-                    items.push_back(0);
-                }
+            const int n_scan_items = p.n_blocks * n_tiles;
+            for (int i = 0; i < n_scan_items; ++i) {
+                const int x = static_cast<int>((static_cast<long long>(i) * 8) / n_scan_items);
+                const int blk = i / n_tiles;
+                per_xcd[x].push_back(s);
+                per_xcd[x].push_back(blk);
+                per_xcd[x].push_back(i - blk * n_tiles);
+                per_xcd[x].push_back(0);
+            }
+        }
+        std::vector<int> items;
+        std::vector<int> bounds(9, 0);
+        for (int x = 0; x < 8; ++x) {
+            items.insert(items.end(), per_xcd[x].begin(), per_xcd[x].end());
+            bounds[x + 1] = static_cast<int>(items.size() / 4);
         }
         q.n_items = static_cast<int>(items.size() / 4);
-        // eight per-XCD queues of equal cost (cost of an item ~ its scan's channels)
-        std::vector<double> cum(q.n_items + 1, 0.0);
-        for (int i = 0; i < q.n_items; ++i) cum[i + 1] = cum[i] + b->plans[items[4 * i]].n_ch;
-        std::vector<int> bounds(9, 0);
-        for (int x = 1; x < 8; ++x)
-            bounds[x] = static_cast<int>(std::lower_bound(cum.begin(), cum.end(), cum.back() * x / 8.0) - cum.begin());
-        bounds[8] = q.n_items;
-        for (int x = 1; x <= 8; ++x) bounds[x] = std::max(bounds[x], bounds[x - 1]);
         q.items_off = all.size() * sizeof(int);
         all.insert(all.end(), items.begin(), items.end());
         q.bounds_off = all.size() * sizeof(int);

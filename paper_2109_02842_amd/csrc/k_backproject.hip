@@ -357,7 +357,10 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         float cr = 0.f, ci = 0.f;
         int off = 0;
         if (c < a.n_ch && pvalid) {
-            const GatherTileEntry& e = tt[c];   // wavefront-uniform
+            // wavefront-uniform and immutable during the launch: read through
+            // the constant address space (scalar loads)
+            const GatherTileEntry& e = *reinterpret_cast<const __attribute__((address_space(4))) GatherTileEntry*>(
+                reinterpret_cast<unsigned long long>(tt + c));
             // range offset from the tile centre (see GatherTileEntry)
             const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
             float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
@@ -503,10 +506,14 @@ __global__ void gather_table_kernel(BpgArgs a, const double* __restrict__ chan, 
 // workgroup takes items from its own XCD's queue (so an XCD's L2 sees a
 // compact set of range profiles) and, once it is empty, from the others in
 // turn; it leaves after all eight are exhausted.
+// wsr and ws are the same batch workspace: wsr for what the kernel only
+// reads (range profiles, tile tables), ws for the spectra it writes; the
+// regions are disjoint, and the separate restrict views let the tile-table
+// reads use scalar loads.
 template <int KB, int RSC>
 __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_batch_kernel(
     const BatchScanDesc* __restrict__ scans, const int4* __restrict__ items, const int* __restrict__ bounds,
-    unsigned* __restrict__ counters, char* __restrict__ ws) {
+    unsigned* __restrict__ counters, const char* __restrict__ wsr, char* __restrict__ ws) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     // the item index travels in the first word of the weight slots, which
     // are free between items (no static LDS: it would cost a workgroup per
@@ -519,14 +526,18 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_batch_ke
         for (;;) {
             if (threadIdx.x == 0) *next = lo + static_cast<int>(atomicAdd(counters + x, 1u));
             __syncthreads();
-            const int it = *next;
+            // wavefront-uniform (readfirstlane): the item's scan, block and
+            // tile then address the descriptors and tile tables with scalar loads
+            const int it = __builtin_amdgcn_readfirstlane(*next);
             __syncthreads();  // every thread has read `next` before it is overwritten
             if (it >= hi) break;
             const int4 w = items[it];
-            const BatchScanDesc& d = scans[w.x];
-            gather_tile<KB, RSC>(d.a, reinterpret_cast<const float2*>(ws + d.q_off),
-                                 reinterpret_cast<const GatherTileEntry*>(ws + d.tab_off),
-                                 reinterpret_cast<float2*>(ws + d.g_off), w.y, w.z, smem);
+            const int sc = __builtin_amdgcn_readfirstlane(w.x), blk = __builtin_amdgcn_readfirstlane(w.y),
+                      tile = __builtin_amdgcn_readfirstlane(w.z);
+            const BatchScanDesc& d = scans[sc];
+            gather_tile<KB, RSC>(d.a, reinterpret_cast<const float2*>(wsr + d.q_off),
+                                 reinterpret_cast<const GatherTileEntry*>(wsr + d.tab_off),
+                                 reinterpret_cast<float2*>(ws + d.g_off), blk, tile, smem);
             __syncthreads();  // LDS is reused by the next item
         }
     }
@@ -883,7 +894,7 @@ int launch_gather_batch(const void* descs, const void* items, const int* bounds,
 #define PL_GB(KB, RSC)                                                                                          \
     if (kb == KB && rsc == RSC) {                                                                               \
         hipLaunchKernelGGL((backproject_gather_batch_kernel<KB, RSC>), dim3(blocks), dim3(64 * kGatherWaves), smem, \
-                           s, args_descs, args_items, bounds, counters, ws);                                    \
+                           s, args_descs, args_items, bounds, counters, ws, ws);                                \
         return check_launch("batched back-projection");                                                         \
     }
     PL_GATHER_CLASSES(PL_GB)
