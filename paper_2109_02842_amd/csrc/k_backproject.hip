@@ -358,9 +358,13 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         int off = 0;
         if (c < a.n_ch && pvalid) {
             // wavefront-uniform and immutable during the launch: read through
-            // the constant address space (scalar loads)
-            const GatherTileEntry& e = *reinterpret_cast<const __attribute__((address_space(4))) GatherTileEntry*>(
+            // the constant address space (scalar loads; device pass only)
+#if defined(__HIP_DEVICE_COMPILE__)
+            const GatherTileEntry e = *reinterpret_cast<const __attribute__((address_space(4))) GatherTileEntry*>(
                 reinterpret_cast<unsigned long long>(tt + c));
+#else
+            const GatherTileEntry e = tt[c];
+#endif
             // range offset from the tile centre (see GatherTileEntry)
             const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
             float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
