@@ -182,8 +182,8 @@ def main() -> int:
     ap.add_argument("--l-oversample", type=float, default=6.0)
     ap.add_argument("--kz-per-lane", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1],
-                    help="1: back-projection on the matrix cores (BF16/FP16 modes)")
+    ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1, 2],
+                    help="1: back-projection on the matrix cores (BF16/FP16 modes); 2: its single-pass FP16 form")
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--kz-block", type=int, default=0)
     ap.add_argument("--range-method", default="nufft", choices=["nufft", "resample"],
@@ -308,11 +308,13 @@ def main() -> int:
     bp_ms = stage["backproject"]
     achieved = FLOP_PER_TERM * terms / (bp_ms * 1e-3) / 1e12
     if plan.mfma_backprojection:
-        # algorithmic flops against the dense BF16 matrix-core peak; the
-        # kernel issues 6 MFMA 16x16x32 per (4x4 pixels, 16 k_z, channel)
+        # algorithmic flops against the dense BF16 / FP16 matrix-core peak;
+        # the kernel issues 6 (split) or 2 (single pass) MFMA 16x16x32 per
+        # (4x4 pixels, 16 k_z, channel)
+        n_mfma = 2 if plan.bp_kernel == "mfma-1pass" else 6
         roof = {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
                 "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
-                "issued_tflops": 6 * 2 * 16 * 16 * 32 / 256 * terms / (bp_ms * 1e-3) / 1e12}
+                "issued_tflops": n_mfma * 2 * 16 * 16 * 32 / 256 * terms / (bp_ms * 1e-3) / 1e12}
     else:
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "frac": achieved / FP32_VECTOR_PEAK_TFLOPS}
@@ -343,7 +345,8 @@ def main() -> int:
         out["variants"] = {}
         for name, prec, mbp, rm in (("bf16", "bf16", 0, "nufft"), ("fp16", "fp16", 0, "nufft"),
                                     ("fp32", "fp32", 0, "nufft"), ("bf16-mfma-bp", "bf16", 1, "nufft"),
-                                    ("fp16-mfma-bp", "fp16", 1, "nufft"), ("fp32-resample", "fp32", 0, "resample")):
+                                    ("fp16-mfma-bp", "fp16", 1, "nufft"), ("fp16-mfma-bp-1pass", "fp16", 2, "nufft"),
+                                    ("fp32-resample", "fp32", 0, "resample")):
             if prec == args.precision and mbp == args.mfma_bp and rm == args.range_method:
                 continue
             vopts = dict(opts, precision=prec, mfma_backprojection=mbp, range_method=rm)

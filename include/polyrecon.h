@@ -183,6 +183,7 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
 #define PL_BP_KZ_LANES 0     /* VALU, one k_z bin per lane, weights broadcast */
 #define PL_BP_PIXEL_LANES 1  /* VALU, one pixel per lane, weights shared via LDS */
 #define PL_BP_MFMA 2         /* matrix cores, split-BF16 operands */
+#define PL_BP_MFMA_SP 3      /* matrix cores, single-pass scaled FP16 operands */
 
 /*
  * Options of the hybrid method.  Zero-initialised fields take the defaults.
@@ -219,6 +220,17 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 oversampling makes them wider the plan lowers it (not below 4).
  *                 Its tile is tile x tile_y pixels (16x16 by default; 8x8,
  *                 16x8 and 16x16 allowed).
+ *                 2 = the same kernel in single-pass form (FP16 mode only,
+ *                 else PL_EUNSUPPORTED): the range compression writes the
+ *                 profiles as FP16 Re / Im planes times one power of two
+ *                 chosen from the strengths' exponents so that no value
+ *                 reaches 2^15, the interpolation x carrier operand is
+ *                 rounded once to FP16, and each pair takes one product
+ *                 (FP32 accumulation).  Every term then carries two FP16
+ *                 roundings (relative 2^-11 each): image error about 3e-4
+ *                 relative L2 against the exact sum instead of the split
+ *                 form's 1e-5, for a third of the matrix-core work.
+ *                 Values above 2: PL_EINVAL.
  * tile, tile_y, kz_per_lane, kz_block and waves are tuning knobs; results
  * agree to the method's tolerance whatever their values.
  *   range_method  PL_RANGE_NUFFT (default) or PL_RANGE_RESAMPLE, the
@@ -262,7 +274,7 @@ typedef struct pl_hybrid_plan_info {
     int32_t window;      /* range samples staged per pixel tile and channel      */
     int32_t tile_x;      /* back-projection pixel tile                           */
     int32_t tile_y;
-    int32_t bp_kernel;   /* back-projection kernel: PL_BP_KZ_LANES, PL_BP_PIXEL_LANES, PL_BP_MFMA */
+    int32_t bp_kernel;   /* back-projection kernel: PL_BP_KZ_LANES, PL_BP_PIXEL_LANES, PL_BP_MFMA, PL_BP_MFMA_SP */
     int32_t waves;       /* wavefronts per back-projection workgroup             */
     double du;           /* range-grid step (m of rho_T + rho_R)                 */
     double beta;         /* exponential-of-semicircle kernel shape               */

@@ -25,7 +25,7 @@ PL_OK, PL_EINVAL, PL_EGEOM, PL_EDEVICE, PL_EWORKSPACE, PL_EUNSUPPORTED = 0, -1, 
 PL_MONO, PL_MULTI = 0, 1
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 INTERPS = {"bspline4": 0, "lagrange4": 1, "linear": 2}
-BP_KERNELS = {0: "kz-lanes", 1: "pixel-lanes", 2: "mfma"}
+BP_KERNELS = {0: "kz-lanes", 1: "pixel-lanes", 2: "mfma", 3: "mfma-1pass"}
 RANGE_METHODS = {"nufft": 0, "resample": 1}
 WARN_ELEMENT_SPACING, WARN_SCAN_STEP = 1, 2
 
@@ -254,7 +254,7 @@ class PlanInfo:
 
     @property
     def mfma_backprojection(self) -> bool:
-        return self.bp_kernel == "mfma"
+        return self.bp_kernel in ("mfma", "mfma-1pass")
 
 
 def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:

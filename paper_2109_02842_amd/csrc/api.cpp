@@ -80,7 +80,8 @@ int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     info->window = p.window;
     info->tile_x = p.tile_x;
     info->tile_y = p.tile_y;
-    info->bp_kernel = p.bp_mfma ? PL_BP_MFMA : (p.bp_gather ? PL_BP_PIXEL_LANES : PL_BP_KZ_LANES);
+    info->bp_kernel = p.bp_mfma ? (p.bp_mfma_sp ? PL_BP_MFMA_SP : PL_BP_MFMA)
+                                : (p.bp_gather ? PL_BP_PIXEL_LANES : PL_BP_KZ_LANES);
     info->waves = p.waves;
     info->du = p.du;
     info->beta = p.beta;

@@ -79,6 +79,7 @@ struct HybridPlan {
     double sigma_l = 6.0, tol = 1e-6;
     int force_tile = 0, force_tile_y = 0, force_kpl = 0, force_waves = 0, force_bp_mfma = 0, force_kb = 0;
     bool bp_mfma = false;            // back-projection on the matrix cores (split-BF16 q)
+    bool bp_mfma_sp = false;         // its single-pass form (scaled FP16 q, one product per pair)
     bool bp_gather = false;          // VALU back-projection with one pixel per lane
     int range_method = PL_RANGE_NUFFT;
     double dkl = 0, k0 = 0, dk = 0;  // resampling: uniform k_L step, frequency grid start and step
@@ -98,11 +99,12 @@ struct HybridPlan {
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
     size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_tw_scan = 0, off_tw_fine = 0;
-    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0, total = 0;
+    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0, off_qexp = 0,
+           total = 0;
 };
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
-size_t backproject_mfma_lds_bytes(int n_ch, int kz_block);
+size_t backproject_mfma_lds_bytes(int n_ch, int kz_block, bool single_pass);
 size_t backproject_gather_lds_bytes(int rows, int row_chunks);
 
 // Batched pixel-per-lane back-projection (one persistent launch for several

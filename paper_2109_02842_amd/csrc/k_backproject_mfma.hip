@@ -28,6 +28,15 @@
 // K-index order: lane group kg = lane / 16 of an operand holds samples
 // {4h .. 4h+3, 8+4h .. 8+4h+3} (h = kg & 1) of the real (kg < 2) or the
 // imaginary (kg >= 2) plane, so each A fragment is two aligned 8-byte reads.
+//
+// Single-pass form (SP): the profiles arrive as two FP16 planes per
+// (channel, k_z), Re and Im, scaled by one power of two 2^-g for the whole
+// call so that every value lies below 2^15 (the scale and g are set by the
+// range compression).  The operand B is rounded once to FP16 and each pair
+// takes one v_mfma_f32_16x16x32_f16 per output part (FP32 accumulation); the
+// result is multiplied by 2^g.  LDS rows are 17 chunks: Re in [0, 8), Im in
+// [8, 16), chunk 16 padding.  Each product then carries two FP16 roundings
+// (relative 2^-11 each) instead of the split form's FP32-class error.
 #include <cstring>
 
 #include "device.hpp"
@@ -37,18 +46,22 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kRowChunks = 33;              // 16-byte chunks per LDS row
-constexpr int kRowBytes = 16 * kRowChunks;  // 528
+constexpr int kRowChunks = 33;              // 16-byte chunks per LDS row (split form)
+constexpr int kRowChunksSP = 17;            // single-pass form
 constexpr int kPlaneBytes = 128;            // 8 chunks per plane
+__host__ __device__ constexpr int row_chunks(bool sp) { return sp ? kRowChunksSP : kRowChunks; }
 constexpr int kSelEntries = 20;             // selector table: a0 = 4h - d0 in [-15, 4]
 
 struct BpmArgs {
     int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, win_bytes;
+    const int* qexp;  // single-pass form: the profiles' scale exponent g
     double x0, y0, dx, dy, inv_du, reach;
     float coef[4][4];  // tap j weight = sum_k coef[j][k] t^k, taps at floor(u) - 1 + j
     double kref[kMaxBlocks];
@@ -57,6 +70,11 @@ struct BpmArgs {
 // Two floats to a packed BF16 pair (round to nearest even), one instruction.
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
     return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2{lo, hi}), bf16x2));
+}
+
+// Two floats to a packed FP16 pair (round to nearest even), one instruction.
+__device__ __forceinline__ unsigned pack_f16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2{lo, hi}), f16x2));
 }
 
 // Split x = hi + lo for the two values packed in h (BF16 pair of (x0, x1)).
@@ -96,14 +114,14 @@ __device__ __forceinline__ double sqrt_dp(double x) {
         unsigned char* dst0_ = (DST0);                                             \
         _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                        \
             const int i_ = wave + NW * j_;                                         \
-            if (i_ * 64 < KB * kRowChunks && doff[j_] != ~0u)                      \
+            if (i_ * 64 < KB * RC && doff[j_] != ~0u)                              \
                 PL_DMA16(base_ + doff[j_], dst0_ + i_ * 1024);                     \
         }                                                                          \
     } while (0)
 
 // Eight-wavefront workgroups aim at four wavefronts per SIMD (two
 // workgroups per CU), which caps a wavefront at 128 registers.
-template <int GPW, int KT, int NW>
+template <int GPW, int KT, int NW, bool SP>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 1)))
 void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                                                                const double* __restrict__ chan,
@@ -114,8 +132,9 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     constexpr int GX = NG == 4 ? 2 : 4, GY = NG / GX;
     static_assert(NG == 4 || NG == 8 || NG == 16, "8x8, 16x8 or 16x16 pixel tiles");
     constexpr int TX = 4 * GX, TY = 4 * GY;
-    constexpr int NIW = (KB * kRowChunks + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
-    constexpr unsigned kBufBytes = KB * kRowBytes;
+    constexpr int RC = row_chunks(SP), RB = 16 * RC, NP = SP ? 2 : 4;  // row chunks, row bytes, planes
+    constexpr int NIW = (KB * RC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
+    constexpr unsigned kBufBytes = KB * RB;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int* win = reinterpret_cast<int*>(smem);
     u32x4* sel_tab = reinterpret_cast<u32x4*>(smem + a.win_bytes);
@@ -162,13 +181,14 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
 #pragma unroll
     for (int j = 0; j < NIW; ++j) {
         const int g = (wave + NW * j) * 64 + lane;
-        const int r = g / kRowChunks, jj = g - r * kRowChunks;
+        const int r = g / RC, jj = g - r * RC;
         const int part = jj >> 3, k8 = jj & 7;
         const int kz = min(blk * KB + r, a.n_z - 1);
-        doff[j] = (r < KB && jj < 32 && k8 < a.nck) ? static_cast<unsigned>(((kz * 4 + part) * a.n_l + 8 * k8) * 2)
-                                                   : ~0u;
+        doff[j] = (r < KB && jj < 8 * NP && k8 < a.nck)
+                      ? static_cast<unsigned>(((kz * NP + part) * a.n_l + 8 * k8) * 2)
+                      : ~0u;
     }
-    const size_t chan_elems = static_cast<size_t>(a.n_z) * 4 * a.n_l;
+    const size_t chan_elems = static_cast<size_t>(a.n_z) * NP * a.n_l;
 
     // pixel of this lane within a group, k' group of the MFMA operands
     const int pn = lane & 15, kg = lane >> 4, h = kg & 1;
@@ -195,9 +215,9 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     __syncthreads();
 
     // LDS byte offset of this lane's A operand within a buffer: row m = lane
-    // & 15 of a k_z tile, hi plane (0 real, 2 imaginary), samples 4h.. of the
-    // group window; the lo plane is kPlaneBytes further
-    const unsigned a_lane = static_cast<unsigned>(pn * kRowBytes) + (kg < 2 ? 0u : 2u * kPlaneBytes) + 8u * h;
+    // & 15 of a k_z tile, hi plane (split: 0 real, 2 imaginary; SP: 0, 1),
+    // samples 4h.. of the group window; the lo plane is kPlaneBytes further
+    const unsigned a_lane = static_cast<unsigned>(pn * RB) + (kg < 2 ? 0u : (SP ? 1u : 2u) * kPlaneBytes) + 8u * h;
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
@@ -258,6 +278,28 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                 const float cb = kg < 2 ? cin : crn;   // rows of Im Q: -Im B, Re B
                 const float r0 = w[0] * ca, r1 = w[1] * ca, r2 = w[2] * ca, r3 = w[3] * ca;
                 const float i0 = w[0] * cb, i1 = w[1] * cb, i2 = w[2] * cb, i3 = w[3] * cb;
+                const unsigned char* ap = smem + bufo + a_lane + 2u * static_cast<unsigned>(sr);
+                if constexpr (SP) {
+                    const unsigned rh0 = pack_f16(r0, r1), rh1 = pack_f16(r2, r3);
+                    const unsigned ih0 = pack_f16(i0, i1), ih1 = pack_f16(i2, i3);
+                    u32x4 vr, vi;
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        vr[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
+                        vi[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
+                    }
+                    const f16x8 br = __builtin_bit_cast(f16x8, vr), bi = __builtin_bit_cast(f16x8, vi);
+#pragma unroll
+                    for (int t = 0; t < KT; ++t) {
+                        const unsigned char* p = ap + t * 16 * RB;
+                        const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
+                        const u32x2 h1 = *reinterpret_cast<const u32x2*>(p + 16);
+                        const f16x8 va = __builtin_bit_cast(f16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
+                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, br, accr[g][t], 0, 0, 0);
+                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, bi, acci[g][t], 0, 0, 0);
+                    }
+                    continue;
+                }
                 const unsigned rh0 = pack_bf16(r0, r1), rh1 = pack_bf16(r2, r3);
                 const unsigned ih0 = pack_bf16(i0, i1), ih1 = pack_bf16(i2, i3);
                 const unsigned rl0 = pack_lo(r0, r1, rh0), rl1 = pack_lo(r2, r3, rh1);
@@ -272,10 +314,9 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                 }
                 const bf16x8 brh = __builtin_bit_cast(bf16x8, vrh), brl = __builtin_bit_cast(bf16x8, vrl);
                 const bf16x8 bih = __builtin_bit_cast(bf16x8, vih), bil = __builtin_bit_cast(bf16x8, vil);
-                const unsigned char* ap = smem + bufo + a_lane + 2u * static_cast<unsigned>(sr);
 #pragma unroll
                 for (int t = 0; t < KT; ++t) {
-                    const unsigned char* p = ap + t * 16 * kRowBytes;
+                    const unsigned char* p = ap + t * 16 * RB;
                     const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
                     const u32x2 h1 = *reinterpret_cast<const u32x2*>(p + 16);
                     const u32x2 l0 = *reinterpret_cast<const u32x2*>(p + kPlaneBytes);
@@ -296,6 +337,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     }
 
     // D layout: lane holds column (pixel) lane & 15, rows 4 (lane / 16) + v
+    const float osc = SP ? ldexpf(1.f, *a.qexp) : 1.f;
 #pragma unroll
     for (int g = 0; g < GPW; ++g) {
         if (gpx[g] < a.nx && gpy[g] < a.ny) {
@@ -305,17 +347,17 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int kz = blk * KB + 16 * t + 4 * kg + v;
-                    if (kz < a.n_z) out[kz] = make_float2(accr[g][t][v], acci[g][t][v]);
+                    if (kz < a.n_z) out[kz] = make_float2(accr[g][t][v] * osc, acci[g][t][v] * osc);
                 }
             }
         }
     }
 }
 
-template <int GPW, int KT, int NW>
+template <int GPW, int KT, int NW, bool SP>
 int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, const unsigned short* qs,
                const double* chan, const double* llo, float2* G) {
-    auto fn = backproject_mfma_kernel<GPW, KT, NW>;
+    auto fn = backproject_mfma_kernel<GPW, KT, NW, SP>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
@@ -328,8 +370,8 @@ int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, co
 
 }  // namespace
 
-size_t backproject_mfma_lds_bytes(int n_ch, int kz_block) {
-    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + kSelEntries * 16 + 2ull * kz_block * kRowBytes;
+size_t backproject_mfma_lds_bytes(int n_ch, int kz_block, bool single_pass) {
+    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + kSelEntries * 16 + 2ull * kz_block * 16 * row_chunks(single_pass);
 }
 
 int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs, char* ws,
@@ -346,6 +388,7 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
     a.per_xcd = (a.n_work + 7) / 8;
     a.nck = p.window / 8;
     a.win_bytes = ((p.n_ch + 3) & ~3) * 4;
+    a.qexp = reinterpret_cast<const int*>(ws + p.off_qexp);
     a.x0 = p.x0;
     a.y0 = p.y0;
     a.dx = p.dx;
@@ -354,17 +397,19 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
     a.reach = std::hypot((p.tile_x - 1) * p.dx, (p.tile_y - 1) * p.dy);  // 2 x tile half-diagonal
     std::memcpy(a.coef, p.coef, sizeof(a.coef));
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
-    if (p.window % 8 || a.nck < 2 || a.nck > 8 || p.window > p.n_l || p.window_pad != kRowChunks)
+    if (p.window % 8 || a.nck < 2 || a.nck > 8 || p.window > p.n_l || p.window_pad != row_chunks(p.bp_mfma_sp))
         return fail(PL_EUNSUPPORTED, "MFMA back-projection window %d out of range", p.window);
-    const size_t smem = backproject_mfma_lds_bytes(p.n_ch, p.block);
+    const size_t smem = backproject_mfma_lds_bytes(p.n_ch, p.block, p.bp_mfma_sp);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "MFMA back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
     const int ng = p.tile_x * p.tile_y / 16;
     const int kt = p.block / 16;
     const int nw = p.waves;
-#define PL_BPM(G_, K_, W_) \
-    if (ng == G_ * W_ && kt == K_ && nw == W_) return launch_cfg<G_, K_, W_>(a, smem, blocks, s, qs, dt.chan, llo, G);
+#define PL_BPM(G_, K_, W_)                                                                              \
+    if (ng == G_ * W_ && kt == K_ && nw == W_)                                                          \
+        return p.bp_mfma_sp ? launch_cfg<G_, K_, W_, true>(a, smem, blocks, s, qs, dt.chan, llo, G)      \
+                            : launch_cfg<G_, K_, W_, false>(a, smem, blocks, s, qs, dt.chan, llo, G);
     PL_BPM(1, 4, 4) PL_BPM(1, 8, 4) PL_BPM(2, 4, 4) PL_BPM(2, 8, 4) PL_BPM(4, 4, 4) PL_BPM(4, 8, 4)
     PL_BPM(1, 4, 8) PL_BPM(1, 8, 8) PL_BPM(2, 4, 8)
 #undef PL_BPM

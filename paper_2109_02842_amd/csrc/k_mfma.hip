@@ -12,6 +12,15 @@
 // phasor phase k'_f u_i is formed in float64 and range-reduced before the
 // float32 sin/cos.  FP16 strengths carry a power-of-2 scale per (k_z,
 // channel) so their largest part sits near 2^14.
+//
+// Output forms: complex64 profiles; four BF16 planes per (channel, k_z) (Re
+// hi, Re lo, Im hi, Im lo) for the split matrix-core back-projection; or two
+// FP16 planes (Re, Im) times one power of two 2^-g for the whole call, for
+// its single-pass form.  With m(k_z, c) the largest |Re|, |Im| of the
+// strengths of a pair, |Re Q|, |Im Q| <= 2 n_f m (the phasors have modulus 1),
+// so g = ceil(log2 n_f) + 1 + max log2-exponent of m - 14 keeps every FP16
+// value below 2^15 whatever the data; FP16's exponent range leaves values
+// down to 2^-29 of that bound at full relative precision.
 #include "device.hpp"
 
 namespace pl {
@@ -81,7 +90,9 @@ __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict
     if (F16) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        if (mx > 0.f) ex = min(max(14 - ilogbf(mx), -100), 100);
+        // all-zero pairs (padding, evanescent k_z) take the largest exponent,
+        // so they never decide the single-pass scale below
+        ex = mx > 0.f ? min(max(14 - ilogbf(mx), -100), 100) : 100;
     }
     const float sc = ldexpf(1.f, ex);
     T* dst = cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp;
@@ -102,6 +113,23 @@ __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict
 
 __device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
 
+// Scale exponent g of the single-pass FP16 profiles (see the header): one
+// workgroup takes the smallest strength exponent over all (k_z, channel).
+__global__ __launch_bounds__(1024) void profile_scale_kernel(const int* __restrict__ se, int n, int log2_nf,
+                                                             int* __restrict__ qexp) {
+    __shared__ int part[16];
+    int m = 100;
+    for (int i = threadIdx.x; i < n; i += 1024) m = min(m, se[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) m = min(m, part[w]);
+        qexp[0] = log2_nf + 1 - m;
+    }
+}
+
 __device__ __forceinline__ unsigned short bf16_of(float x) {
     return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
 }
@@ -109,14 +137,16 @@ __device__ __forceinline__ unsigned short bf16_of(float x) {
 // One block = one k_z bin x 128 range samples; wavefront w owns rows
 // [32 w, 32 w + 32) of that range block and keeps its phasor operand A' for
 // all of K' in registers, then walks the channel tiles of 32.
-// SPLIT: instead of complex64 profiles, write four BF16 planes per
+// OUT: kOutC64 complex64 profiles; kOutSplit four BF16 planes per
 // (channel, k_z) -- Re hi, Re lo, Im hi, Im lo with x = hi + lo -- the
-// operand layout of the matrix-core back-projection.
-template <bool F16, int NCH, bool SPLIT>
+// operand layout of the split matrix-core back-projection; kOutF16 two FP16
+// planes (Re, Im) scaled by 2^-qexp[0], that of its single-pass form.
+constexpr int kOutC64 = 0, kOutSplit = 1, kOutF16 = 2;
+template <bool F16, int NCH, int OUT>
 __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16>::T* __restrict__ cs,
                                                          const int* __restrict__ se,
                                                          const double* __restrict__ kp, MfmaArgs a,
-                                                         void* __restrict__ qout) {
+                                                         const int* __restrict__ qexp, void* __restrict__ qout) {
     typedef typename Half<F16>::T T;
     typedef typename Half<F16>::V V;
     constexpr int NC = NCH;          // chunks of 16 in K' = 2 n_fp, NC = n_fp / 8
@@ -181,8 +211,29 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
             acci = Half<F16>::mfma(al[qq], vb2h, acci);
         }
         if (c < a.n_ch) {
-            const float sc = ldexpf(1.f, -se[static_cast<size_t>(kap) * a.n_chp + c]);
-            if constexpr (SPLIT) {
+            const int ex = se[static_cast<size_t>(kap) * a.n_chp + c];
+            if constexpr (OUT == kOutF16) {
+                const float sc = ldexpf(1.f, -ex - qexp[0]);
+                _Float16* dst = static_cast<_Float16*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 2 * a.n_l;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int r = row0 + 8 * g + 4 * (lane >> 5);
+                    if (r < a.n_l) {
+                        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+                        h4 vr, vi;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            vr[k] = static_cast<_Float16>(accr[4 * g + k] * sc);
+                            vi[k] = static_cast<_Float16>(acci[4 * g + k] * sc);
+                        }
+                        *reinterpret_cast<h4*>(dst + r) = vr;
+                        *reinterpret_cast<h4*>(dst + a.n_l + r) = vi;
+                    }
+                }
+                continue;
+            }
+            const float sc = ldexpf(1.f, -ex);
+            if constexpr (OUT == kOutSplit) {
                 // four consecutive rows per lane and plane: one 8-byte store
                 // each (n_l is a multiple of 4)
                 unsigned short* dst =
@@ -222,7 +273,7 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
     }
 }
 
-template <bool F16, bool SPLIT>
+template <bool F16, int OUT>
 int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStream_t s) {
     typedef typename Half<F16>::T T;
     MfmaArgs a{};
@@ -241,13 +292,20 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
                        reinterpret_cast<const float*>(ws + p.off_wk), a, cs, se);
     int rc = check_launch("range compression (strengths)");
     if (rc) return rc;
+    int* qexp = reinterpret_cast<int*>(ws + p.off_qexp);
+    if (OUT == kOutF16) {
+        int log2_nf = 0;
+        while ((1 << log2_nf) < p.n_f) ++log2_nf;
+        hipLaunchKernelGGL(profile_scale_kernel, dim3(1), dim3(1024), 0, s, se, static_cast<int>(waves), log2_nf, qexp);
+        if ((rc = check_launch("range compression (profile scale)"))) return rc;
+    }
     const long long blocks = static_cast<long long>(p.n_z) * ((p.n_l + 127) / 128);
     const double* kp = reinterpret_cast<const double*>(ws + p.off_kp);
     switch (p.n_fp / 8) {
 #define PL_NC(N)                                                                                          \
     case N:                                                                                               \
-        hipLaunchKernelGGL((range_mfma_kernel<F16, N, SPLIT>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
-                           kp, a, q);                                                                     \
+        hipLaunchKernelGGL((range_mfma_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
+                           kp, a, qexp, q);                                                               \
         break;
         PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
 #undef PL_NC
@@ -261,14 +319,20 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
 
 int launch_range_compress_mfma(const HybridPlan& p, const float2* spec, char* ws, float2* q, hipStream_t s) {
     if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
-    return p.precision == PL_PREC_FP16 ? run_mfma<true, false>(p, spec, ws, q, s) : run_mfma<false, false>(p, spec, ws, q, s);
+    return p.precision == PL_PREC_FP16 ? run_mfma<true, kOutC64>(p, spec, ws, q, s)
+                                       : run_mfma<false, kOutC64>(p, spec, ws, q, s);
 }
 
 int launch_range_compress_mfma_split(const HybridPlan& p, const float2* spec, char* ws, unsigned short* qs,
                                      hipStream_t s) {
     if (p.n_fp > 128 || p.n_fp % 16 != 0) return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
     if (p.n_l % 4) return fail(PL_EUNSUPPORTED, "split range profiles need n_l divisible by 4");
-    return p.precision == PL_PREC_FP16 ? run_mfma<true, true>(p, spec, ws, qs, s) : run_mfma<false, true>(p, spec, ws, qs, s);
+    if (p.bp_mfma_sp) {
+        if (p.precision != PL_PREC_FP16) return fail(PL_EUNSUPPORTED, "single-pass profiles are FP16");
+        return run_mfma<true, kOutF16>(p, spec, ws, qs, s);
+    }
+    return p.precision == PL_PREC_FP16 ? run_mfma<true, kOutSplit>(p, spec, ws, qs, s)
+                                       : run_mfma<false, kOutSplit>(p, spec, ws, qs, s);
 }
 
 }  // namespace pl

@@ -144,9 +144,15 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // most 3 samples past its window start and its last at most
     // ceil(2 * diagonal / du) + 3 past its first.
     p.bp_mfma = false;
+    p.bp_mfma_sp = false;
+    if (p.force_bp_mfma > 2) return fail(PL_EINVAL, "mfma_backprojection must be -1, 0, 1 or 2");
     if (p.force_bp_mfma > 0) {
         if (p.precision == PL_PREC_FP32)
             return fail(PL_EUNSUPPORTED, "the MFMA back-projection runs in the BF16 / FP16 modes only");
+        // single pass: one FP16 product per pair (scaled FP16 profiles)
+        const bool sp = p.force_bp_mfma == 2;
+        if (sp && p.precision != PL_PREC_FP16)
+            return fail(PL_EUNSUPPORTED, "the single-pass MFMA back-projection runs in the FP16 mode only");
         if (p.force_kpl != 0)
             return fail(PL_EINVAL, "kz_per_lane applies to the VALU back-projection");
         const int tx = p.force_tile ? p.force_tile : 16;
@@ -169,13 +175,14 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         const double rt = 0.5 * std::hypot((tx - 1) * grid->dx, (ty - 1) * grid->dy);
         const int need = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
         const int nck = std::max(2, (need + 7) / 8);
-        const size_t lds = backproject_mfma_lds_bytes(p.n_ch, kb);
+        const size_t lds = backproject_mfma_lds_bytes(p.n_ch, kb, sp);
         if (std::ceil(2.0 * gdiag / p.du) <= 9 && nck <= 8 && lds <= kMaxLds && p.n_f <= 128) {
             p.bp_mfma = true;
+            p.bp_mfma_sp = sp;
             p.tile_x = tx;
             p.tile_y = ty;
             p.window = 8 * nck;  // samples staged per plane and row
-            p.window_pad = 33;   // LDS row length in 16-byte chunks (4 planes x 8 + 1)
+            p.window_pad = sp ? 17 : 33;  // LDS row length in 16-byte chunks (2 or 4 planes x 8 + 1)
             p.waves = p.force_waves ? p.force_waves : ((tx * ty >= 128 && kb == 64) ? 8 : 4);
             if (tx * ty == 64 && p.waves == 8)
                 return fail(PL_EUNSUPPORTED, "8 wavefronts need a 16x8 or 16x16 MFMA tile");
@@ -362,10 +369,12 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         if (p.n_fp > 128)
             return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
         p.off_mfma_a = take(nz * static_cast<size_t>(p.n_chp) * 4);
+        p.off_qexp = take(4);
         p.off_mfma_b = take(nz * static_cast<size_t>(p.n_chp) * 4 * p.n_fp * 2);
     } else {
         p.off_mfma_a = off;
         p.off_mfma_b = off;
+        p.off_qexp = off;
     }
     p.total = off;
     *out = p;

@@ -205,6 +205,26 @@ def test_mfma_backprojection_plan_rules():
     assert "reconstruct_hybrid" in pr.last_error()
 
 
+def test_mfma_single_pass_plan_rules():
+    g = pr.make_geometry(W.C1.array)
+    fine = _fine_grid(40, 40, 0.0015)
+    p = pr.hybrid_plan_info(g, fine, precision="fp16", mfma_backprojection=2)
+    assert p.bp_kernel == "mfma-1pass" and p.mfma_backprojection and p.tile == (16, 16)
+    split = pr.hybrid_plan_info(g, fine, precision="fp16", mfma_backprojection=1)
+    assert split.bp_kernel == "mfma" and split.window == p.window and split.n_l == p.n_l
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="bf16", mfma_backprojection=2)   # FP16 operands only
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="fp32", mfma_backprojection=2)
+    assert e.value.code == pr.PL_EUNSUPPORTED
+    with pytest.raises(pr.PolyreconError) as e:
+        pr.hybrid_plan_info(g, fine, precision="fp16", mfma_backprojection=3)
+    assert e.value.code == pr.PL_EINVAL
+    assert pr.hybrid_plan_info(pr.make_geometry(W.C2.array), W.C2.grid, precision="fp16",
+                               mfma_backprojection=2).bp_kernel == "mfma-1pass"
+
+
 def test_valu_backprojection_plan_rules():
     g = pr.make_geometry(W.C2.array)
     p = pr.hybrid_plan_info(g, W.C2.grid)

@@ -312,6 +312,73 @@ def test_mfma_backprojection_tilings(tile, tile_y, kb, waves):
     assert err < 1e-3
 
 
+@pytest.mark.parametrize("interp", ["bspline4", "lagrange4", "linear"])
+@pytest.mark.parametrize("case", ["tiny-multi", "multi-small", "C1"])
+def test_mfma_single_pass_matches_oracle(case, interp):
+    # one FP16 product per pair: two FP16 roundings (2^-11 relative) per
+    # term, held to the reduced-precision bar of 1e-3 relative L2
+    wl = {"tiny-multi": W.tiny("multi"), "multi-small": multi_small(), "C1": W.C1}[case]
+    grid = {"tiny-multi": _fine_grid(21, 11, 0.0015), "multi-small": _fine_grid(27, 35, 0.0015),
+            "C1": _fine_grid(44, 37, 0.0015)}[case]
+    sigma = 16.0 if interp == "lagrange4" else 8.0
+    g = pr.make_geometry(wl.array)
+    kw = dict(precision="fp16", interp=interp, l_oversample=sigma)
+    plan = pr.hybrid_plan_info(g, grid, mfma_backprojection=2, **kw)
+    assert plan.bp_kernel == "mfma-1pass" and plan.tile == (16, 16) and plan.block == 64
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 51)
+    say("mfma single pass", case, interp, "window", plan.window)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), mfma_backprojection=2, **kw))
+    ref = ohyb.image(arr, grid, s)
+    err = rel(img, ref)
+    err_valu = rel(host(pr.reconstruct_hybrid(g, grid, dev(s), mfma_backprojection=-1, **kw)), ref)
+    say("   rel L2", err, "VALU back-projection", err_valu)
+    assert np.isfinite(img).all()
+    assert err < (1e-3 if interp != "linear" else 1.2 * err_valu + 1e-3)
+
+
+@pytest.mark.parametrize("tile,tile_y,kb,waves", [(8, 8, 64, 4), (8, 8, 128, 4), (16, 8, 64, 4), (16, 8, 128, 4),
+                                                   (16, 16, 64, 4), (16, 16, 128, 4), (16, 8, 64, 8),
+                                                   (16, 8, 128, 8), (16, 16, 64, 8)])
+def test_mfma_single_pass_tilings(tile, tile_y, kb, waves):
+    # ragged k_z blocks (300 bins) and ragged tiles (61 x 45 pixels)
+    arr_desc = replace(W.C1.array, n_scan=300)
+    grid = _fine_grid(61, 45, 0.0015)
+    g = pr.make_geometry(arr_desc)
+    arr = ogeom.build(arr_desc)
+    s = W.random_echo(arr_desc, 53)
+    say("mfma single-pass tiling", tile, tile_y, kb, waves)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), precision="fp16", mfma_backprojection=2, tile=tile,
+                                     tile_y=tile_y, kz_block=kb, waves=waves))
+    kap = sorted(set(W.random_subset(300, 6, 54).tolist() + [0, 63, 64, 127, 128, 299]))
+    pix = np.unique(np.concatenate([W.random_subset(grid.nx * grid.ny, 200, 55), [0, grid.nx * grid.ny - 1]]))
+    px, py = ohyb.pixel_grid(grid)
+    ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
+    err = rel(_spectrum_subset(img, kap, pix), ref)
+    say("   rel L2", err)
+    assert err < 1e-3
+
+
+@pytest.mark.parametrize("scale", [1e-15, 1.0, 1e15])
+def test_mfma_single_pass_follows_the_data_scale(scale):
+    # the FP16 profiles' power-of-two scale comes from the data: echoes 15
+    # decades apart reconstruct to the same relative error, and a zero echo
+    # to an exactly zero image
+    wl = W.C1
+    grid = _fine_grid(44, 37, 0.0015)
+    g = pr.make_geometry(wl.array)
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 57) * scale
+    say("mfma single pass, echo scale", scale)
+    img = host(pr.reconstruct_hybrid(g, grid, dev(s), precision="fp16", mfma_backprojection=2))
+    err = rel(img, ohyb.image(arr, grid, s))
+    say("   rel L2", err)
+    assert np.isfinite(img).all() and err < 1e-3
+    if scale == 1.0:
+        zero = host(pr.reconstruct_hybrid(g, grid, dev(np.zeros_like(s)), precision="fp16", mfma_backprojection=2))
+        assert not np.any(zero)
+
+
 @pytest.mark.parametrize("wlname", ["tiny-mono", "tiny-multi", "multi-small", "C1"])
 @pytest.mark.parametrize("interp", ["bspline4", "lagrange4"])
 def test_hybrid_end_to_end_small(wlname, interp):
