@@ -11,7 +11,9 @@ tuned once per device.
 
 Every candidate computes the same image to the method's tolerance (the
 options only change launch shapes and, through the k_z block size, the
-range-grid step), so the choice is a pure speed decision.
+range-grid step), so the choice is a pure speed decision.  The single-pass
+FP16 matrix-core form (``mfma_backprojection=2``) is a precision choice, not
+a launch shape: asked for, it is tuned over its own tilings only.
 """
 from __future__ import annotations
 
@@ -37,7 +39,10 @@ MFMA_CANDIDATES = tuple(
 def candidates(geom: Geometry, grid, precision: str = "fp32", **fixed) -> List[dict]:
     """Option sets the planner accepts for this problem (``fixed`` options,
     e.g. the interpolation, are added to each)."""
-    pool = VALU_CANDIDATES + (MFMA_CANDIDATES if precision != "fp32" else ())
+    if fixed.get("mfma_backprojection") == 2:
+        pool = tuple(dict(c, mfma_backprojection=2) for c in MFMA_CANDIDATES)
+    else:
+        pool = VALU_CANDIDATES + (MFMA_CANDIDATES if precision != "fp32" else ())
     out, seen = [], set()
     for c in pool:
         opts = dict(fixed, precision=precision, **c)

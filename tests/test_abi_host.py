@@ -351,6 +351,10 @@ def test_autotune_candidates_and_cache(tmp_path):
     assert not any(o.get("mfma_backprojection") for o in c32)
     cb = at.candidates(g, W.C2.grid, "bf16")
     assert any(o.get("mfma_backprojection") for o in cb) and len(cb) > len(c32)
+    # the single-pass form, once asked for, is tuned over its own tilings
+    c1p = at.candidates(g, W.C2.grid, "fp16", mfma_backprojection=2)
+    assert c1p and all(pr.hybrid_plan_info(g, W.C2.grid, **o).bp_kernel == "mfma-1pass" for o in c1p)
+    assert len({(o["tile"], o["tile_y"], o["kz_block"], o["waves"]) for o in c1p}) == len(c1p)
     # coarse pixels: every request maps to the k_z-per-lane kernel, listed once per shape
     g1, coarse = pr.make_geometry(W.C1.array), W.ImageGrid.centred(16, 0.30)
     c1 = at.candidates(g1, coarse, "fp32")
