@@ -218,6 +218,13 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     // & 15 of a k_z tile, hi plane (split: 0 real, 2 imaginary; SP: 0, 1),
     // samples 4h.. of the group window; the lo plane is kPlaneBytes further
     const unsigned a_lane = static_cast<unsigned>(pn * RB) + (kg < 2 ? 0u : (SP ? 1u : 2u) * kPlaneBytes) + 8u * h;
+    // Each 8-byte piece of an A fragment is read from its own base register
+    // (offsets the compiler cannot see): adjacent pieces would otherwise be
+    // merged into ds_read2_b64, which serves fewer lanes per cycle, and rows
+    // 4 dwords apart then share banks.  A separate ds_read_b64 serves half a
+    // wavefront per cycle, conflict-free in this layout.
+    unsigned dq[3] = {16u, kPlaneBytes, kPlaneBytes + 16u};
+    asm volatile("" : "+v"(dq[0]), "+v"(dq[1]), "+v"(dq[2]));
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
@@ -293,7 +300,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                     for (int t = 0; t < KT; ++t) {
                         const unsigned char* p = ap + t * 16 * RB;
                         const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
-                        const u32x2 h1 = *reinterpret_cast<const u32x2*>(p + 16);
+                        const u32x2 h1 = *reinterpret_cast<const u32x2*>(ap + dq[0] + t * 16 * RB);
                         const f16x8 va = __builtin_bit_cast(f16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
                         accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, br, accr[g][t], 0, 0, 0);
                         acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, bi, acci[g][t], 0, 0, 0);
@@ -318,9 +325,9 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                 for (int t = 0; t < KT; ++t) {
                     const unsigned char* p = ap + t * 16 * RB;
                     const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
-                    const u32x2 h1 = *reinterpret_cast<const u32x2*>(p + 16);
-                    const u32x2 l0 = *reinterpret_cast<const u32x2*>(p + kPlaneBytes);
-                    const u32x2 l1 = *reinterpret_cast<const u32x2*>(p + kPlaneBytes + 16);
+                    const u32x2 h1 = *reinterpret_cast<const u32x2*>(ap + dq[0] + t * 16 * RB);
+                    const u32x2 l0 = *reinterpret_cast<const u32x2*>(ap + dq[1] + t * 16 * RB);
+                    const u32x2 l1 = *reinterpret_cast<const u32x2*>(ap + dq[2] + t * 16 * RB);
                     const bf16x8 vah = __builtin_bit_cast(bf16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
                     const bf16x8 val = __builtin_bit_cast(bf16x8, u32x4{l0[0], l0[1], l1[0], l1[1]});
                     accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brh, accr[g][t], 0, 0, 0);
