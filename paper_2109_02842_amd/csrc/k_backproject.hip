@@ -435,6 +435,9 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
                 const float4* cp = reinterpret_cast<const float4*>(rp + r * RSC * 16);
                 const float4 q01 = cp[0], q23 = cp[1];
                 const float2 q4 = *reinterpret_cast<const float2*>(cp + 2);
+                // keeps the next row's 8-byte read from merging with this
+                // one into a ds_read2_b64 (fewer lanes per cycle, bank conflicts)
+                asm volatile("" ::: "memory");
                 const float re = wa.x * q01.x + wa.y * q01.z + wa.z * q23.x + wa.w * q23.z + wb.x * q4.x;
                 const float im = wa.x * q01.y + wa.y * q01.w + wa.z * q23.y + wa.w * q23.w + wb.x * q4.y;
                 acc[r].x = fmaf(wb.y, re, acc[r].x);
