@@ -118,8 +118,21 @@ __device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
 __global__ __launch_bounds__(1024) void profile_scale_kernel(const int* __restrict__ se, int n, int log2_nf,
                                                              int* __restrict__ qexp) {
     __shared__ int part[16];
-    int m = 100;
-    for (int i = threadIdx.x; i < n; i += 1024) m = min(m, se[i]);
+    // sixteen independent loads in flight per thread: the one workgroup is
+    // bound by load latency, not bandwidth
+    int mv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) mv[j] = 100;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 16 * 1024) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int i = i0 + j * 1024;
+            if (i < n) mv[j] = min(mv[j], se[i]);
+        }
+    }
+    int m = mv[0];
+#pragma unroll
+    for (int j = 1; j < 16; ++j) m = min(m, mv[j]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
