@@ -20,6 +20,9 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kLanes = 64;          // wavefront width on gfx950
 constexpr int kMaxScan = 4096;
 constexpr int kMaxBlocks = kMaxScan / kLanes;  // k_z blocks of at least one bin per lane
+// single-pass FP16 profiles: workgroups of the exponent reduction; the
+// workspace slot holds their parts, then the scale exponent g
+constexpr int kProfileScaleParts = 64;
 constexpr size_t kMaxLds = 160 * 1024;          // LDS per workgroup on gfx950
 constexpr int kMaxFreq = 1024;
 constexpr int kMaxFine = 4096;      // NUFFT fine grid held twice in LDS (64 KiB)

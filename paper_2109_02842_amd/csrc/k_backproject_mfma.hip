@@ -344,7 +344,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     }
 
     // D layout: lane holds column (pixel) lane & 15, rows 4 (lane / 16) + v
-    const float osc = SP ? ldexpf(1.f, *a.qexp) : 1.f;
+    const float osc = SP ? ldexpf(1.f, a.qexp[kProfileScaleParts]) : 1.f;
 #pragma unroll
     for (int g = 0; g < GPW; ++g) {
         if (gpx[g] < a.nx && gpy[g] < a.ny) {

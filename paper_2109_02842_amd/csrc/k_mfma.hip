@@ -113,34 +113,29 @@ __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict
 
 __device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
 
-// Scale exponent g of the single-pass FP16 profiles (see the header): one
-// workgroup takes the smallest strength exponent over all (k_z, channel).
-__global__ __launch_bounds__(1024) void profile_scale_kernel(const int* __restrict__ se, int n, int log2_nf,
-                                                             int* __restrict__ qexp) {
-    __shared__ int part[16];
-    // sixteen independent loads in flight per thread: the one workgroup is
-    // bound by load latency, not bandwidth
-    int mv[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) mv[j] = 100;
-    for (int i0 = threadIdx.x; i0 < n; i0 += 16 * 1024) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int i = i0 + j * 1024;
-            if (i < n) mv[j] = min(mv[j], se[i]);
-        }
-    }
-    int m = mv[0];
-#pragma unroll
-    for (int j = 1; j < 16; ++j) m = min(m, mv[j]);
+// Scale exponent g of the single-pass FP16 profiles (see the header), in
+// two steps: kProfileScaleParts workgroups each take the smallest strength
+// exponent of their share of (k_z, channel) into part[b]; every workgroup of
+// the contraction then reduces the parts itself (one load per lane) and the
+// first one stores g for the back-projection in part[kProfileScaleParts].
+__global__ __launch_bounds__(256) void profile_scale_kernel(const int* __restrict__ se, int n, int* __restrict__ part) {
+    __shared__ int wmin[4];
+    const int per = (n + kProfileScaleParts - 1) / kProfileScaleParts;
+    const int lo = blockIdx.x * per, hi = min(n, lo + per);
+    int m = 100;
+    for (int i = lo + threadIdx.x; i < hi; i += 256) m = min(m, se[i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < 16; ++w) m = min(m, part[w]);
-        qexp[0] = log2_nf + 1 - m;
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+}
+
+__device__ __forceinline__ int profile_scale(const int* __restrict__ part, int log2_nf) {
+    int m = (threadIdx.x & 63) < kProfileScaleParts ? part[threadIdx.x & 63] : 100;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o));
+    return log2_nf + 1 - m;
 }
 
 __device__ __forceinline__ unsigned short bf16_of(float x) {
@@ -153,13 +148,15 @@ __device__ __forceinline__ unsigned short bf16_of(float x) {
 // OUT: kOutC64 complex64 profiles; kOutSplit four BF16 planes per
 // (channel, k_z) -- Re hi, Re lo, Im hi, Im lo with x = hi + lo -- the
 // operand layout of the split matrix-core back-projection; kOutF16 two FP16
-// planes (Re, Im) scaled by 2^-qexp[0], that of its single-pass form.
+// planes (Re, Im) scaled by 2^-g, that of its single-pass form (g from the
+// exponent parts in qexp[0, kProfileScaleParts), stored to
+// qexp[kProfileScaleParts]).
 constexpr int kOutC64 = 0, kOutSplit = 1, kOutF16 = 2;
 template <bool F16, int NCH, int OUT>
 __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16>::T* __restrict__ cs,
                                                          const int* __restrict__ se,
                                                          const double* __restrict__ kp, MfmaArgs a,
-                                                         const int* __restrict__ qexp, void* __restrict__ qout) {
+                                                         int* __restrict__ qexp, int log2_nf, void* __restrict__ qout) {
     typedef typename Half<F16>::T T;
     typedef typename Half<F16>::V V;
     constexpr int NC = NCH;          // chunks of 16 in K' = 2 n_fp, NC = n_fp / 8
@@ -169,6 +166,11 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
     const int ib = blockIdx.x - kap * n_ib;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = ib * 128 + wave * 32;
+    int gexp = 0;
+    if constexpr (OUT == kOutF16) {
+        gexp = profile_scale(qexp, log2_nf);
+        if (blockIdx.x == 0 && threadIdx.x == 0) qexp[kProfileScaleParts] = gexp;
+    }
     if (row0 >= a.n_l) return;  // no barriers in this kernel
     const int i = row0 + (lane & 31);
     const int kh = 8 * (lane >> 5);  // this lane's k' offset inside a chunk
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
         if (c < a.n_ch) {
             const int ex = se[static_cast<size_t>(kap) * a.n_chp + c];
             if constexpr (OUT == kOutF16) {
-                const float sc = ldexpf(1.f, -ex - qexp[0]);
+                const float sc = ldexpf(1.f, -ex - gexp);
                 _Float16* dst = static_cast<_Float16*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 2 * a.n_l;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
@@ -306,10 +308,10 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
     int rc = check_launch("range compression (strengths)");
     if (rc) return rc;
     int* qexp = reinterpret_cast<int*>(ws + p.off_qexp);
+    int log2_nf = 0;
+    while ((1 << log2_nf) < p.n_f) ++log2_nf;
     if (OUT == kOutF16) {
-        int log2_nf = 0;
-        while ((1 << log2_nf) < p.n_f) ++log2_nf;
-        hipLaunchKernelGGL(profile_scale_kernel, dim3(1), dim3(1024), 0, s, se, static_cast<int>(waves), log2_nf, qexp);
+        hipLaunchKernelGGL(profile_scale_kernel, dim3(kProfileScaleParts), dim3(256), 0, s, se, static_cast<int>(waves), qexp);
         if ((rc = check_launch("range compression (profile scale)"))) return rc;
     }
     const long long blocks = static_cast<long long>(p.n_z) * ((p.n_l + 127) / 128);
@@ -318,7 +320,7 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
 #define PL_NC(N)                                                                                          \
     case N:                                                                                               \
         hipLaunchKernelGGL((range_mfma_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
-                           kp, a, qexp, q);                                                               \
+                           kp, a, qexp, log2_nf, q);                                                      \
         break;
         PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
 #undef PL_NC

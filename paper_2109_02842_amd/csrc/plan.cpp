@@ -369,7 +369,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         if (p.n_fp > 128)
             return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
         p.off_mfma_a = take(nz * static_cast<size_t>(p.n_chp) * 4);
-        p.off_qexp = take(4);
+        p.off_qexp = take(4 * (kProfileScaleParts + 1));
         p.off_mfma_b = take(nz * static_cast<size_t>(p.n_chp) * 4 * p.n_fp * 2);
     } else {
         p.off_mfma_a = off;
