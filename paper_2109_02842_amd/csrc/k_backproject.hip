@@ -243,13 +243,13 @@ int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s
 // KB k_z bins; lane = pixel, wavefront w owns k_z rows [RW w, RW (w + 1)).
 // The weights and carrier of a (pixel, channel) pair are computed once per
 // workgroup (wavefront w for the w-th channel of a batch of 4, at the start
-// of the batch) and shared through LDS, so nothing is broadcast per pixel.  Every
-// LDS read is a 16-byte aligned ds_read_b128 (8-byte aligned pairs run at
-// about half the rate on gfx950): a pixel reads the aligned samples
-// [2m, 2m + 5) around its four taps (two 16-byte reads and one 8-byte read,
-// m = first tap / 2) with five weights shifted by the parity of the first
-// tap (one of them zero), so a (pixel, k_z) term costs 40 bytes of LDS and
-// fourteen FMAs.  The channel's window rows (even start)
+// of the batch) and shared through LDS, so nothing is broadcast per pixel.  A
+// pixel reads its four tap samples with four ds_read_b64 (32 bytes of LDS
+// and twelve FMAs per (pixel, k_z) term).  The reads are kept apart by an
+// empty asm with a memory clobber: the compiler would pair adjacent ones
+// into ds_read2_b64, which serves fewer lanes per cycle on gfx950 (paired,
+// this form ran slower than two aligned 16-byte reads of five samples with
+// a zero weight; unpaired it is 9 % faster).  The channel's window rows (even start)
 // are copied into LDS by 16-byte direct global-to-LDS loads one channel
 // ahead, double-buffered.  The kernel is bound by instruction issue with
 // its latencies covered by other workgroups: LDS per workgroup (8 KiB of
@@ -300,8 +300,8 @@ constexpr int kGatherBatch = 4;   // channels per weight batch
 // [floor(A) - 3, floor(A) - 2] (even), so a first tap f = floor(u) - 1 has
 // f - s in [1, ceil(B - A) + 2], at most the window length minus 6 (the
 // planner's window is ceil(2 reach / du) + 8 samples or more: the bound
-// plus one sample against float rounding).  A pixel reads the aligned
-// samples [(f - s) & ~1, + 5), inside the window while f - s <= wpl - 5.
+// plus one sample against float rounding).  A pixel reads the samples
+// [f - s, f - s + 4), inside the window while f - s <= wpl - 4.
 // One (k_z block, tile) work item; tab = the scan's tile table; smem = the
 // workgroup's LDS (the weight slots, then the two row buffers).
 template <int KB, int RSC>
@@ -350,10 +350,9 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const float oo = ox * ox + oy * oy;
 
     // weights of (this lane's pixel, channel c) into slot [wave]:
-    // five tap weights over the aligned samples (first tap's parity decides
-    // the shift), carrier, byte offset of the first chunk in the row
+    // four tap weights, carrier, byte offset of the first tap in the row
     auto weights = [&](int c) {
-        float w[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float w[4] = {0.f, 0.f, 0.f, 0.f};
         float cr = 0.f, ci = 0.f;
         int off = 0;
         if (c < a.n_ch && pvalid) {
@@ -379,27 +378,20 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             const float t = uu - fv;
             // within the window by the bound above; the clamp keeps every read
             // inside the staged row whatever the rounding
-            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 5));
-            const bool odd = i0 & 1;
-            float v[4];
+            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 4));
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                v[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
-            w[0] = odd ? 0.f : v[0];
-            w[1] = odd ? v[0] : v[1];
-            w[2] = odd ? v[1] : v[2];
-            w[3] = odd ? v[2] : v[3];
-            w[4] = odd ? v[3] : 0.f;
+                w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
             // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
             const float2 c0 = cis_rev(kref_rev * e.lc);
             const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
             cr = c0.x * c1.x - c0.y * c1.y;
             ci = c0.x * c1.y + c0.y * c1.x;
-            off = (i0 & ~1) * 8;
+            off = i0 * 8;
         }
         float4* slot = wts + wave * 2 * 64 + lane;
         slot[0] = make_float4(w[0], w[1], w[2], w[3]);
-        slot[64] = make_float4(w[4], cr, ci, __int_as_float(off));
+        slot[64] = make_float4(cr, ci, __int_as_float(off), 0.f);
     };
 
     float2 acc[RW];
@@ -428,22 +420,25 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             if (c + 1 < a.n_ch) PL_STAGE_Q(c + 1, (c + 1) & 1, __builtin_amdgcn_readlane(wins, cc));
             const float4* slot = wts + cc * 2 * 64 + lane;
             const float4 wa = slot[0], wb = slot[64];
-            const unsigned off = __float_as_uint(wb.w);
+            const unsigned off = __float_as_uint(wb.z);
             const unsigned char* rp = smem + lds_q + (c & 1) * kBufBytes + row0 + off;
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
-                const float4* cp = reinterpret_cast<const float4*>(rp + r * RSC * 16);
-                const float4 q01 = cp[0], q23 = cp[1];
-                const float2 q4 = *reinterpret_cast<const float2*>(cp + 2);
-                // keeps the next row's 8-byte read from merging with this
-                // one into a ds_read2_b64 (fewer lanes per cycle, bank conflicts)
-                asm volatile("" ::: "memory");
-                const float re = wa.x * q01.x + wa.y * q01.z + wa.z * q23.x + wa.w * q23.z + wb.x * q4.x;
-                const float im = wa.x * q01.y + wa.y * q01.w + wa.z * q23.y + wa.w * q23.w + wb.x * q4.y;
-                acc[r].x = fmaf(wb.y, re, acc[r].x);
-                acc[r].x = fmaf(-wb.z, im, acc[r].x);
-                acc[r].y = fmaf(wb.y, im, acc[r].y);
-                acc[r].y = fmaf(wb.z, re, acc[r].y);
+                const float2* cp = reinterpret_cast<const float2*>(rp + r * RSC * 16);
+                // four separate 8-byte reads: the empty asm keeps the
+                // compiler from pairing them into ds_read2_b64
+                float2 q[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    q[j] = cp[j];
+                    asm volatile("" ::: "memory");
+                }
+                const float re = wa.x * q[0].x + wa.y * q[1].x + wa.z * q[2].x + wa.w * q[3].x;
+                const float im = wa.x * q[0].y + wa.y * q[1].y + wa.z * q[2].y + wa.w * q[3].y;
+                acc[r].x = fmaf(wb.x, re, acc[r].x);
+                acc[r].x = fmaf(-wb.y, im, acc[r].x);
+                acc[r].y = fmaf(wb.x, im, acc[r].y);
+                acc[r].y = fmaf(wb.y, re, acc[r].y);
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();

@@ -248,7 +248,7 @@ def _gather_window_margins(wl):
     returns the smallest distance of any pixel's range position u (in
     samples from s) to the two limits that keep its reads inside the
     window: u >= 1 (first tap floor(u) - 1 >= 0) and u < window - 3 (first
-    tap at most window - 5, whose aligned five-sample read ends inside).
+    tap at most window - 5; the four-sample reads need window - 4).
     The range grid starts at each channel's lowest range over the pixel
     rectangle minus two samples.
     """
