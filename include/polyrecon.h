@@ -227,7 +227,7 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 reaches 2^15, the interpolation x carrier operand is
  *                 rounded once to FP16, and each pair takes one product
  *                 (FP32 accumulation).  Every term then carries two FP16
- *                 roundings (relative 2^-11 each): image error about 3e-4
+ *                 roundings (relative 2^-11 each): image error 2-3e-4
  *                 relative L2 against the exact sum instead of the split
  *                 form's 1e-5, for a third of the matrix-core work.
  *                 Values above 2: PL_EINVAL.
