@@ -560,7 +560,8 @@ def test_binding_rejects_bad_tensors():
 def _small_batch():
     """Uneven scans: pixel-per-lane scans of different sizes, one whose pixels
     are too coarse for it (k_z-per-lane kernel), one BF16 scan on the matrix
-    cores; every kind of back-projection the batch call launches."""
+    cores and one FP16 scan in their single-pass form; every kind of
+    back-projection the batch call launches."""
     c1 = W.C1
     ms = multi_small()
     scans = [
@@ -569,6 +570,7 @@ def _small_batch():
         (ms.array, _fine_grid(27, 35, 0.004), {}),
         (c1.array, W.ImageGrid.centred(16, 0.30), {}),                        # coarse: k_z per lane
         (replace(c1.array, n_scan=32), _fine_grid(40, 40, 0.0015), dict(precision="bf16", mfma_backprojection=1)),
+        (replace(c1.array, n_scan=40), _fine_grid(36, 44, 0.0015), dict(precision="fp16", mfma_backprojection=2)),
     ]
     return scans
 
