@@ -281,6 +281,9 @@ typedef struct pl_hybrid_plan_info {
     size_t workspace_bytes;
     int32_t range_method;/* PL_RANGE_NUFFT or PL_RANGE_RESAMPLE                  */
     double dk_uniform;   /* PL_RANGE_RESAMPLE: step of the uniform k_L grid, 2 pi / (n_fine du); else 0 */
+    int32_t scan_fft_len;/* length the scan / k_z transforms run through: n_scan when it is  */
+                         /* 2,3,5-smooth, else the chirp-z length (smooth, >= 2 n_scan - 1)  */
+    int32_t reserved_;
 } pl_hybrid_plan_info;
 
 /*
@@ -381,6 +384,7 @@ int adjoint_hybrid(const pl_geometry* geom, const pl_image_grid* grid, const pl_
  * those options) and return PL_EUNSUPPORTED if it is 1.  Buffers are device
  * memory:
  *   scan_fft:        echo [c][m][f] -> spec [c][kz][f]        (eq. 2/12)
+ *       S[c][kz][f] = sum_m s[c][m][f] exp(-2 pi i kz m / n_scan) (unnormalised).
  *   range_compress:  spec [c][kz][f] -> q [c][kz][n_l]        (eq. 8a/19a)
  *       q[c][kz][i] approximates sum_f w_f k_f S e^{j k'_f l_i} with
  *       k' = k_rho - k_ref(block of kz), l_i = l_lo[c] + i du, where w_f is
@@ -388,11 +392,20 @@ int adjoint_hybrid(const pl_geometry* geom, const pl_image_grid* grid, const pl_
  *       1 / sinc^4(k'_f du / 2) (q then holds spline coefficients).
  *   backproject:     q -> G [p][kz] with p = iy * nx + ix      (eq. 8b/19b)
  *   kz_ifft:         G [p][kz] -> image [z][y][x]              (eq. 9)
- * range_lo_host, if not NULL, receives l_lo[c] (n_channels doubles).
- * ws must be at least hybrid_workspace_bytes; range_compress and backproject
- * use it for their tables.
+ *       g[z][p] = (1 / n_scan) sum_kz G[p][kz] exp(+2 pi i kz z / n_scan).
+ * The transforms take any n_scan in [1, 4096]: 2,3,5-smooth lengths as
+ * mixed-radix stages, other lengths by Bluestein's chirp-z transform through
+ * a smooth length of at least 2 n_scan - 1 (same result to float rounding).
+ * Their ws holds the transform's tables (fft_workspace_bytes bytes, 256-byte
+ * aligned; written by every call, so calls sharing it must not overlap).
+ * range_lo_host, if not NULL, receives l_lo[c] (n_channels doubles); the
+ * call then waits for the stream.
+ * range_compress and backproject take a ws of at least
+ * hybrid_workspace_bytes for their tables.  None of the four allocates.
  */
-int scan_fft(const pl_geometry* geom, const float* echo_dev, float* spec_dev, hipStream_t stream);
+int fft_workspace_bytes(const pl_geometry* geom, size_t* bytes);
+int scan_fft(const pl_geometry* geom, const float* echo_dev, float* spec_dev, void* ws, size_t ws_bytes,
+             hipStream_t stream);
 int range_compress(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
                    const float* spec_dev, float* q_dev, double* range_lo_host, void* ws,
                    size_t ws_bytes, hipStream_t stream);
@@ -400,7 +413,7 @@ int backproject(const pl_geometry* geom, const pl_image_grid* grid, const pl_hyb
                 const float* q_dev, float* spectrum_dev, void* ws, size_t ws_bytes,
                 hipStream_t stream);
 int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spectrum_dev,
-            float* image_dev, hipStream_t stream);
+            float* image_dev, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------- batches */
 /*

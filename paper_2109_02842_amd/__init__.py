@@ -69,7 +69,8 @@ class HybridPlanInfo(C.Structure):
                 ("kernel_width", C.c_int32), ("n_blocks", C.c_int32), ("block", C.c_int32),
                 ("window", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("bp_kernel", C.c_int32), ("waves", C.c_int32), ("du", C.c_double), ("beta", C.c_double),
-                ("workspace_bytes", C.c_size_t), ("range_method", C.c_int32), ("dk_uniform", C.c_double)]
+                ("workspace_bytes", C.c_size_t), ("range_method", C.c_int32), ("dk_uniform", C.c_double),
+                ("scan_fft_len", C.c_int32), ("reserved_", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -92,12 +93,13 @@ _SIGNATURES = {
                                  C.c_size_t, _P]),
     "reconstruct_hybrid_events": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P,
                                             _P, C.c_size_t, _P, _P]),
-    "scan_fft": (C.c_int, [_P, _P, _P, _P]),
+    "fft_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "scan_fft": (C.c_int, [_P, _P, _P, _P, C.c_size_t, _P]),
     "range_compress": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P, _P,
                                  C.c_size_t, _P]),
     "backproject": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                               C.c_size_t, _P]),
-    "kz_ifft": (C.c_int, [_P, C.POINTER(ImageGridC), _P, _P, _P]),
+    "kz_ifft": (C.c_int, [_P, C.POINTER(ImageGridC), _P, _P, _P, C.c_size_t, _P]),
     "bp_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "reconstruct_bp": (C.c_int, [_P, C.POINTER(ImageGridC), C.c_int32, C.c_int32, _P, _P, _P,
                                  C.c_size_t, _P]),
@@ -251,6 +253,7 @@ class PlanInfo:
     waves: int = 4
     range_method: str = "nufft"
     dk_uniform: float = 0.0         # resampling method: step of the uniform k_L grid (rad/m)
+    scan_fft_len: int = 0           # length the scan / k_z transforms run through (chirp-z if > n_kz)
 
     @property
     def mfma_backprojection(self) -> bool:
@@ -259,14 +262,16 @@ class PlanInfo:
 
 def hybrid_plan_info(geom: Geometry, grid, **opts) -> PlanInfo:
     info = HybridPlanInfo()
-    kref = (C.c_double * 64)()
+    _check(lib().hybrid_plan_info(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
+                                  C.byref(info), None))
+    kref = (C.c_double * max(1, info.n_blocks))()
     _check(lib().hybrid_plan_info(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
                                   C.byref(info), C.cast(kref, _P)))
     return PlanInfo(info.n_kz, info.n_l, info.n_fine, info.kernel_width, info.n_blocks, info.block,
                     info.window, (info.tile_x, info.tile_y), info.du, info.beta,
                     int(info.workspace_bytes), list(kref[: info.n_blocks]), BP_KERNELS[info.bp_kernel],
                     int(info.waves), {v: k for k, v in RANGE_METHODS.items()}[info.range_method],
-                    float(info.dk_uniform))
+                    float(info.dk_uniform), int(info.scan_fft_len))
 
 
 def hybrid_workspace_bytes(geom: Geometry, grid, **opts) -> int:
@@ -493,12 +498,21 @@ def reconstruct_hybrid_events(geom: Geometry, grid, echo, events, out=None, ws=N
     return out
 
 
-def scan_fft(geom: Geometry, echo, out=None):
+def fft_workspace_bytes(geom: Geometry) -> int:
+    n = C.c_size_t()
+    _check(lib().fft_workspace_bytes(geom.handle, C.byref(n)))
+    return int(n.value)
+
+
+def scan_fft(geom: Geometry, echo, out=None, ws=None):
+    """Spectrum S[c][kz][f] = FFT over the scan axis, eq. (2)/(12)."""
     torch = _torch()
     if out is None:
         out = torch.empty(geom.echo_shape, dtype=torch.complex64, device=echo.device)
+    ws = _ws(ws, fft_workspace_bytes(geom))
     _check(lib().scan_fft(geom.handle, _dev_c64(echo, geom.echo_shape, "echo"),
-                          _dev_c64(out, geom.echo_shape, "out"), _stream()))
+                          _dev_c64(out, geom.echo_shape, "out"), C.c_void_p(ws.data_ptr()), ws.numel(),
+                          _stream()))
     return out
 
 
@@ -545,14 +559,16 @@ def backproject(geom: Geometry, grid, q, out=None, ws=None, **opts):
     return out
 
 
-def kz_ifft(geom: Geometry, grid, spectrum, out=None):
+def kz_ifft(geom: Geometry, grid, spectrum, out=None, ws=None):
+    """Image g[z][y][x] = inverse FFT over k_z (1/n), eq. (9)."""
     torch = _torch()
     shape = (geom.n_scan, grid.ny, grid.nx)
     if out is None:
         out = torch.empty(shape, dtype=torch.complex64, device=spectrum.device)
+    ws = _ws(ws, fft_workspace_bytes(geom))
     _check(lib().kz_ifft(geom.handle, C.byref(_grid(grid)),
                          _dev_c64(spectrum, (grid.ny * grid.nx, geom.n_scan), "spectrum"),
-                         _dev_c64(out, shape, "out"), _stream()))
+                         _dev_c64(out, shape, "out"), C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
 
 

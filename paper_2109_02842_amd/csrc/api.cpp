@@ -31,31 +31,15 @@ int prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opt
     return g->device_tables(dt);
 }
 
-// Twiddle table exp(-2 pi i t / n) for the standalone transform calls, kept
-// per (device, n) for the life of the process (a few KiB each).
-int scan_twiddles(int n, hipStream_t stream, float2** out) {
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, float2*> tables;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(PL_EDEVICE, "hipGetDevice failed");
-    std::lock_guard<std::mutex> lock(mu);
-    const auto key = std::make_pair(dev, n);
-    auto it = tables.find(key);
-    if (it != tables.end()) {
-        *out = it->second;
-        return PL_OK;
-    }
-    float2* tw = nullptr;
-    if (hipMalloc(&tw, sizeof(float2) * n) != hipSuccess) return fail(PL_EDEVICE, "twiddle allocation failed");
-    int rc = launch_twiddles(tw, n, stream);
-    if (rc == PL_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(PL_EDEVICE, "twiddle table failed");
-    if (rc) {
-        (void)hipFree(tw);
-        return rc;
-    }
-    tables[key] = tw;
-    *out = tw;
-    return PL_OK;
+// The standalone transform calls: the tables of the length-n_scan transform
+// written into the caller's workspace, checked for size and alignment.
+int axis_tables(const pl_geometry* g, void* ws, size_t ws_bytes, hipStream_t stream, AxisFft* f, const char* what) {
+    int rc = plan_axis_fft(g->n_scan, f);
+    if (rc) return rc;
+    if (!ws) return fail(PL_EWORKSPACE, "%s: null workspace", what);
+    if (!aligned256(ws)) return fail(PL_EWORKSPACE, "%s: workspace must be 256-byte aligned", what);
+    if (ws_bytes < f->bytes) return fail(PL_EWORKSPACE, "%s: workspace of %zu bytes, %zu needed", what, ws_bytes, f->bytes);
+    return launch_axis_fft_tables(*f, static_cast<char*>(ws), stream);
 }
 
 }  // namespace
@@ -88,7 +72,9 @@ int hybrid_plan_info(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     info->workspace_bytes = p.total;
     info->range_method = p.range_method;
     info->dk_uniform = p.range_method == PL_RANGE_RESAMPLE ? p.dkl : 0.0;
-    if (k_ref_host) std::memcpy(k_ref_host, p.kref, sizeof(double) * p.n_blocks);
+    info->scan_fft_len = p.zfft.m;
+    info->reserved_ = 0;
+    if (k_ref_host) std::memcpy(k_ref_host, p.kref, sizeof(double) * p.n_blocks);  // n_blocks <= kMaxBlocks
     return PL_OK;
 }
 
@@ -117,17 +103,26 @@ int simulate_echo(const pl_geometry* g, int32_t n_scat, const double* xyz, const
     return launch_simulate(g, dt, n_scat, xyz, refl, reinterpret_cast<float2*>(echo), stream);
 }
 
-int scan_fft(const pl_geometry* g, const float* echo, float* spec, hipStream_t stream) {
+int fft_workspace_bytes(const pl_geometry* g, size_t* bytes) {
+    using namespace pl;
+    clear_error();
+    if (!g || !bytes) return fail(PL_EINVAL, "fft_workspace_bytes: null pointer");
+    AxisFft f;
+    const int rc = plan_axis_fft(g->n_scan, &f);
+    if (rc) return rc;
+    *bytes = f.bytes;
+    return PL_OK;
+}
+
+int scan_fft(const pl_geometry* g, const float* echo, float* spec, void* ws, size_t ws_bytes, hipStream_t stream) {
     using namespace pl;
     clear_error();
     if (!g || !echo || !spec) return fail(PL_EINVAL, "scan_fft: null pointer");
-    Radices rad;
-    if (!factor_radices(g->n_scan, &rad))
-        return fail(PL_EUNSUPPORTED, "scan_fft: n_scan = %d is not a product of 2, 3 and 5", g->n_scan);
-    float2* tw = nullptr;
-    const int rc = scan_twiddles(g->n_scan, stream, &tw);
+    AxisFft f;
+    const int rc = axis_tables(g, ws, ws_bytes, stream, &f, "scan_fft");
     if (rc) return rc;
-    return launch_scan_fft(g, reinterpret_cast<const float2*>(echo), reinterpret_cast<float2*>(spec), tw, rad, stream);
+    return launch_scan_fft(g, reinterpret_cast<const float2*>(echo), reinterpret_cast<float2*>(spec), f,
+                           static_cast<const char*>(ws), stream);
 }
 
 int range_compress(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* spec,
@@ -168,7 +163,8 @@ int backproject(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid
     return launch_backproject(p, dt, reinterpret_cast<const float2*>(q), w, reinterpret_cast<float2*>(spectrum), stream);
 }
 
-int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectrum, float* image, hipStream_t stream) {
+int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectrum, float* image, void* ws,
+            size_t ws_bytes, hipStream_t stream) {
     using namespace pl;
     clear_error();
     if (!g || !grid || !spectrum || !image) return fail(PL_EINVAL, "kz_ifft: null pointer");
@@ -177,11 +173,10 @@ int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectr
     p.n_z = g->n_scan;
     p.nx = grid->nx;
     p.ny = grid->ny;
-    if (!factor_radices(p.n_z, &p.scan_rad)) return fail(PL_EUNSUPPORTED, "kz_ifft: n_scan not 2,3,5-smooth");
-    float2* tw = nullptr;
-    const int rc = scan_twiddles(g->n_scan, stream, &tw);
+    const int rc = axis_tables(g, ws, ws_bytes, stream, &p.zfft, "kz_ifft");
     if (rc) return rc;
-    return launch_kz_ifft(p, reinterpret_cast<const float2*>(spectrum), reinterpret_cast<float2*>(image), tw, stream);
+    return launch_kz_ifft(p, reinterpret_cast<const float2*>(spectrum), reinterpret_cast<float2*>(image),
+                          static_cast<const char*>(ws), stream);
 }
 
 }  // extern "C"
@@ -208,10 +203,9 @@ int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     float2* spec = reinterpret_cast<float2*>(w + p.off_spec);
     float2* q = reinterpret_cast<float2*>(w + p.off_q);
     float2* G = reinterpret_cast<float2*>(w + p.off_G);
-    const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
+    const char* ztab = w + p.off_zfft;
     if ((rc = mark(0)) || (tables && (rc = launch_plan_tables(p, dt, w, stream)))) return rc;
-    if ((rc = mark(1)) ||
-        (rc = launch_scan_fft(g, reinterpret_cast<const float2*>(echo), spec, tw_scan, p.scan_rad, stream)))
+    if ((rc = mark(1)) || (rc = launch_scan_fft(g, reinterpret_cast<const float2*>(echo), spec, p.zfft, ztab, stream)))
         return rc;
     if ((rc = mark(2))) return rc;
     if (p.bp_mfma) {
@@ -225,7 +219,7 @@ int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_h
         if (rc) return rc;
         if ((rc = mark(3)) || (rc = launch_backproject(p, dt, q, w, G, stream))) return rc;
     }
-    if ((rc = mark(4)) || (rc = launch_kz_ifft(p, G, reinterpret_cast<float2*>(image), tw_scan, stream))) return rc;
+    if ((rc = mark(4)) || (rc = launch_kz_ifft(p, G, reinterpret_cast<float2*>(image), ztab, stream))) return rc;
     return mark(5);
 }
 
@@ -278,12 +272,12 @@ int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     float2* St = reinterpret_cast<float2*>(w + p.off_spec);
     float2* qt = reinterpret_cast<float2*>(w + p.off_q);
     float2* Gt = reinterpret_cast<float2*>(w + p.off_G);
-    const float2* tw_scan = reinterpret_cast<const float2*>(w + p.off_tw_scan);
+    const char* ztab = w + p.off_zfft;
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
-    if ((rc = launch_kz_fft_adjoint(p, reinterpret_cast<const float2*>(image), Gt, tw_scan, stream))) return rc;
+    if ((rc = launch_kz_fft_adjoint(p, reinterpret_cast<const float2*>(image), Gt, ztab, stream))) return rc;
     if ((rc = launch_backproject_adjoint(p, dt, Gt, w, qt, stream))) return rc;  // writes every element of q~
     if ((rc = launch_range_adjoint(p, qt, w, St, stream))) return rc;
-    return launch_scan_fft_adjoint(g, St, reinterpret_cast<float2*>(echo), tw_scan, p.scan_rad, stream);
+    return launch_scan_fft_adjoint(g, St, reinterpret_cast<float2*>(echo), p.zfft, ztab, stream);
 }
 
 int bp_workspace_bytes(const pl_geometry* g, size_t* bytes) {

@@ -200,10 +200,9 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoe
         const HybridPlan& p = b->plans[s];
         char* ws_s = w + b->ws_off[s];
         float2* spec = reinterpret_cast<float2*>(ws_s + p.off_spec);
-        const float2* tw_scan = reinterpret_cast<const float2*>(ws_s + p.off_tw_scan);
         if ((rc = launch_plan_tables(p, dts[s], ws_s, stream))) return rc;
-        if ((rc = launch_scan_fft(b->geoms[s], reinterpret_cast<const float2*>(echoes[s]), spec, tw_scan, p.scan_rad,
-                                  stream)))
+        if ((rc = launch_scan_fft(b->geoms[s], reinterpret_cast<const float2*>(echoes[s]), spec, p.zfft,
+                                  ws_s + p.off_zfft, stream)))
             return rc;
         if (p.bp_mfma)
             rc = launch_range_compress_mfma_split(p, spec, ws_s, reinterpret_cast<unsigned short*>(ws_s + p.off_q),
@@ -237,7 +236,7 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoe
         const HybridPlan& p = b->plans[s];
         char* ws_s = w + b->ws_off[s];
         if ((rc = launch_kz_ifft(p, reinterpret_cast<const float2*>(ws_s + p.off_G), reinterpret_cast<float2*>(images[s]),
-                                 reinterpret_cast<const float2*>(ws_s + p.off_tw_scan), stream)))
+                                 ws_s + p.off_zfft, stream)))
             return rc;
     }
     return PL_OK;

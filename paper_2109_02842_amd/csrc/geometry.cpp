@@ -49,6 +49,36 @@ bool is_fft_friendly(int n) {
     return factor_radices(n, &r);
 }
 
+int plan_axis_fft(int n, AxisFft* out) {
+    if (n < 1 || n > kMaxScan) return fail(PL_EINVAL, "transform length %d outside [1, %d]", n, kMaxScan);
+    AxisFft f;
+    f.n = n;
+    if (factor_radices(n, &f.rad)) {
+        f.m = n;
+    } else {
+        int m = 2 * n - 1;
+        while (m <= kMaxChirpLen && !factor_radices(m, &f.rad)) ++m;
+        if (m > kMaxChirpLen) return fail(PL_EUNSUPPORTED, "transform length %d needs a chirp-z length over %d", n, kMaxChirpLen);
+        f.m = m;
+        f.chirp = true;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~static_cast<size_t>(255);
+        return o;
+    };
+    f.off_tw = take(8ull * f.m);
+    if (f.chirp) {
+        f.off_chirp = take(8ull * f.n);
+        f.off_pad = take(8ull * f.m);
+        f.off_hat = take(8ull * f.m);
+    }
+    f.bytes = off;
+    *out = f;
+    return PL_OK;
+}
+
 }  // namespace pl
 
 int pl_geometry::device_tables(pl::DeviceTables* out) const {

@@ -19,7 +19,9 @@ constexpr double kSpeedOfLight = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kLanes = 64;          // wavefront width on gfx950
 constexpr int kMaxScan = 4096;
-constexpr int kMaxBlocks = kMaxScan / kLanes;  // k_z blocks of at least one bin per lane
+constexpr int kMinBlock = 32;       // fewest k_z bins sharing one reference wavenumber
+constexpr int kMaxBlocks = kMaxScan / kMinBlock;
+constexpr int kMaxChirpLen = 8192;  // longest smooth length a chirp-z transform runs through
 // single-pass FP16 profiles: workgroups of the exponent reduction; the
 // workspace slot holds their parts, then the scale exponent g
 constexpr int kProfileScaleParts = 64;
@@ -48,6 +50,24 @@ struct Radices {
 };
 bool factor_radices(int n, Radices* out);
 bool is_fft_friendly(int n);
+
+// A batched transform of length n along a strided axis (the scan FFT of
+// eq. 2/12 and the k_z inverse FFT of eq. 9).  A 2,3,5-smooth n runs as
+// mixed-radix stages of length m = n; any other n by Bluestein's chirp-z
+// transform through the smallest smooth m >= 2 n - 1.  Its tables live in a
+// caller's buffer at byte offsets from a table base: m twiddles
+// exp(-2 pi i t / m); for the chirp-z form also the chirp exp(-i pi t^2 / n)
+// (n values), the padded conjugate chirp (m values, scratch of the table
+// step) and its forward transform scaled by 1/m (m values).
+struct AxisFft {
+    int n = 0, m = 0;
+    bool chirp = false;
+    Radices rad;  // radices of m
+    size_t off_tw = 0, off_chirp = 0, off_pad = 0, off_hat = 0, bytes = 0;
+};
+int plan_axis_fft(int n, AxisFft* out);
+// Writes the tables of f at `tables` (256-byte aligned, f.bytes long).
+int launch_axis_fft_tables(const AxisFft& f, char* tables, hipStream_t s);
 
 }  // namespace pl
 
@@ -93,7 +113,8 @@ struct HybridPlan {
     int block = kLanes;  // k_z bins sharing one reference wavenumber (64 x bins per lane)
     int n_blocks = 0;
     double kref[kMaxBlocks] = {};
-    Radices scan_rad, fine_rad;
+    AxisFft zfft;        // the scan and k_z transforms (length n_z)
+    Radices fine_rad;
     int n_gl = 0;
     double gl_x[kMaxGL] = {}, gl_w[kMaxGL] = {};
     // back-projection tiling
@@ -101,7 +122,7 @@ struct HybridPlan {
     // interpolation weights w_k(t) = sum_j coef[k][j] t^j, taps at floor(u)-1+k
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
-    size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_tw_scan = 0, off_tw_fine = 0;
+    size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_zfft = 0, off_tw_fine = 0;
     size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0, off_qexp = 0,
            total = 0;
 };
@@ -129,9 +150,9 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
 // the plan tables: reads l_lo); a no-op for plans without that kernel.
 size_t gather_table_bytes(const HybridPlan& p);
 int launch_gather_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
-int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const float2* tw,
-                    const Radices& rad, hipStream_t s);
-int launch_twiddles(float2* tw, int n, hipStream_t s);
+// The transforms take the tables of f at `tables`.
+int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const AxisFft& f, const char* tables,
+                    hipStream_t s);
 int launch_range_compress_fp32(const HybridPlan& p, const float2* spec, char* ws, float2* q,
                                hipStream_t s);
 int launch_range_compress_resample(const HybridPlan& p, const float2* spec, char* ws, float2* q,
@@ -144,15 +165,14 @@ int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2
                        float2* G, hipStream_t s);
 int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs,
                             char* ws, float2* G, hipStream_t s);
-int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw,
-                   hipStream_t s);
+int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const char* tables, hipStream_t s);
 // Adjoint steps (image -> echo), in the order they run.
-int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const float2* tw, hipStream_t s);
+int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const char* tables, hipStream_t s);
 int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, const float2* Gt, char* ws, float2* qt,
                                hipStream_t s);
 int launch_range_adjoint(const HybridPlan& p, const float2* qt, char* ws, float2* St, hipStream_t s);
-int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const float2* tw,
-                            const Radices& rad, hipStream_t s);
+int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const AxisFft& f,
+                            const char* tables, hipStream_t s);
 int launch_simulate(const pl_geometry* g, const DeviceTables& dt, int n_scat, const double* xyz,
                     const double* refl, float2* echo, hipStream_t s);
 int launch_bp(const pl_geometry* g, const DeviceTables& dt, const pl_image_grid* grid, int iz0,

@@ -24,16 +24,16 @@ __device__ double dist_to_rect(double px, double py, double x0, double x1, doubl
 //                rectangle minus two steps)
 //   lref[c]      range rho_T + rho_R from channel c to the centre of the pixel
 //                rectangle (demodulation reference of the resampling method)
-//   tw_scan[t]   exp(-2 pi i t / n_z);  tw_fine[t]  exp(-2 pi i t / n_fine)
+//   tw_fine[t]   exp(-2 pi i t / n_fine)
 //   deap[i]      1 / (h * FT of the spreading kernel) at output mode i - n_l/2
 //   kp[kz][f]    k' = k_rho - k_ref(block), k_rho = sqrt(k^2 - k_z^2/4) (0 if evanescent)
 //   wk[kz][f]    k_f (weight of "k dk") times the B-spline prefilter, 0 if evanescent
 __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ chan,
                                    const double* __restrict__ k, double* __restrict__ llo,
-                                   double* __restrict__ lref, float2* __restrict__ tw_scan, float2* __restrict__ tw_fine,
+                                   double* __restrict__ lref, float2* __restrict__ tw_fine,
                                    float* __restrict__ deap, double* __restrict__ kp,
                                    float* __restrict__ wk) {
-    const long long n0 = a.n_ch, n1 = n0 + a.n_z, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
+    const long long n0 = a.n_ch, n1 = n0, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
     const long long total = n3 + static_cast<long long>(a.n_z) * a.n_f;
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < total;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
@@ -44,11 +44,6 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
             llo[c] = lmin - 2.0 * a.du;
             const double cx = 0.5 * (a.gx0 + a.gx1), cy = 0.5 * (a.gy0 + a.gy1);
             lref[c] = hypot(cx - chan[4 * c], cy - chan[4 * c + 1]) + hypot(cx - chan[4 * c + 2], cy - chan[4 * c + 3]);
-        } else if (idx < n1) {
-            const int t = static_cast<int>(idx - n0);
-            double s, c;
-            sincospi(-2.0 * t / a.n_z, &s, &c);
-            tw_scan[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
         } else if (idx < n2) {
             const int t = static_cast<int>(idx - n1);
             double s, c;
@@ -84,16 +79,40 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
     }
 }
 
-__global__ void twiddle_kernel(float2* tw, int n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    double s, c;
-    sincospi(-2.0 * t / n, &s, &c);
-    tw[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
+// Tables of an AxisFft (see internal.hpp): tw[t] = exp(-2 pi i t / m); for
+// the chirp-z form w[t] = exp(-i pi t^2 / n), t < n, with t^2 reduced mod 2n
+// in integers so that the float64 sine and cosine see an argument below 2;
+// pad[j] = conj(w[t]) for j = t < n and j = m - t (0 < t < n), else 0 (the
+// filter of the cyclic convolution; its transform is taken next).
+__global__ void axis_fft_tables_kernel(int n, int m, int chirp, float2* __restrict__ tw, float2* __restrict__ w,
+                                       float2* __restrict__ pad) {
+    const int total = m + (chirp ? n + m : 0);
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        double s, c;
+        if (idx < m) {
+            sincospi(-2.0 * idx / m, &s, &c);
+            tw[idx] = make_float2(static_cast<float>(c), static_cast<float>(s));
+        } else if (idx < m + n) {
+            const long long t = idx - m;
+            const long long r = (t * t) % (2LL * n);
+            sincospi(-static_cast<double>(r) / n, &s, &c);
+            w[t] = make_float2(static_cast<float>(c), static_cast<float>(s));
+        } else {
+            const int j = idx - m - n;
+            const long long t = j < n ? j : (j > m - n ? m - j : -1);
+            float2 v = make_float2(0.f, 0.f);
+            if (t >= 0) {
+                const long long r = (t * t) % (2LL * n);
+                sincospi(static_cast<double>(r) / n, &s, &c);
+                v = make_float2(static_cast<float>(c), static_cast<float>(s));
+            }
+            pad[j] = v;
+        }
+    }
 }
 
 struct FftArgs {
-    int n, nbatch, inner, per_wg, ld, sign, n_fast_in, n_fast_out;
+    int n, m, nbatch, inner, per_wg, ld, sign, n_fast_in, n_fast_out;
     long long in_so, in_si, in_sn, out_so, out_si, out_sn;
     float scale, inv_inner;
     Radices rad;
@@ -140,6 +159,72 @@ __global__ __launch_bounds__(256) void fft_strided_kernel(const float2* __restri
         const int b = b0 + t;
         const int o = b / a.inner, s = b - o * a.inner;
         out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(res[t * a.ld + i], a.scale);
+    }
+}
+
+// Bluestein's chirp-z transform (1970) for lengths that are not 2,3,5-smooth.
+// With t k = (t^2 + k^2 - (k - t)^2) / 2 and w[t] = exp(-i pi t^2 / n),
+//   X[k] = sum_t x[t] exp(-2 pi i t k / n) = w[k] sum_t (x[t] w[t]) conj(w[k - t]),
+// a linear convolution of length 2n - 1, evaluated as a cyclic one of the
+// smooth length m >= 2n - 1: forward transform of x w zero-padded to m,
+// product with hat = FFT_m(pad) / m, inverse transform, times w[k] for k < n.
+// The inverse transform (sign +1) conjugates its input and output.  Each
+// block transforms per_wg batches in LDS (two buffers of per_wg * ld values,
+// ld = m + 1); batch and element indexing as in fft_strided_kernel.
+__global__ __launch_bounds__(256) void fft_chirp_strided_kernel(const float2* __restrict__ in,
+                                                                float2* __restrict__ out,
+                                                                const float2* __restrict__ tw,
+                                                                const float2* __restrict__ w,
+                                                                const float2* __restrict__ hat, FftArgs a) {
+    extern __shared__ float2 smem[];
+    float2* A = smem;
+    float2* B = smem + a.per_wg * a.ld;
+    const int b0 = blockIdx.x * a.per_wg;
+    const int nb = min(a.per_wg, a.nbatch - b0);
+    const int tid = threadIdx.x;
+    const bool inv = a.sign > 0;
+    for (int e = tid; e < nb * (a.m - a.n); e += blockDim.x) {
+        const int t = e / (a.m - a.n);
+        A[t * a.ld + a.n + (e - t * (a.m - a.n))] = make_float2(0.f, 0.f);
+    }
+    const int total = nb * a.n;
+    for (int e = tid; e < total; e += blockDim.x) {
+        int t, i;
+        if (a.n_fast_in) {
+            t = e / a.n;
+            i = e - t * a.n;
+        } else {
+            i = e / nb;
+            t = e - i * nb;
+        }
+        const int b = b0 + t;
+        const int o = b / a.inner, s = b - o * a.inner;
+        float2 v = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+        if (inv) v.y = -v.y;
+        A[t * a.ld + i] = cmul(v, w[i]);
+    }
+    __syncthreads();
+    float2* r = lds_fft(A, B, a.m, a.ld, nb, a.rad, tw, -1, tid, blockDim.x);
+    for (int e = tid; e < nb * a.m; e += blockDim.x) {
+        const int t = e / a.m, i = e - t * a.m;
+        r[t * a.ld + i] = cmul(r[t * a.ld + i], hat[i]);
+    }
+    __syncthreads();
+    r = lds_fft(r, r == A ? B : A, a.m, a.ld, nb, a.rad, tw, +1, tid, blockDim.x);
+    for (int e = tid; e < total; e += blockDim.x) {
+        int t, i;
+        if (a.n_fast_out) {
+            t = e / a.n;
+            i = e - t * a.n;
+        } else {
+            i = e / nb;
+            t = e - i * nb;
+        }
+        const int b = b0 + t;
+        const int o = b / a.inner, s = b - o * a.inner;
+        float2 v = cmul(r[t * a.ld + i], w[i]);
+        if (inv) v.y = -v.y;
+        out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(v, a.scale);
     }
 }
 
@@ -220,16 +305,26 @@ int launch_fft_wave(const FftArgs& a, const float2* in, float2* out, const float
     return check_launch(what);
 }
 
-int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nbatch, int inner,
+int set_lds_limit(const void* fn, size_t smem, const char* what) {
+    if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "%s: LDS of %zu bytes exceeds the workgroup's", what, smem);
+    if (smem > 65536 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem)) != hipSuccess)
+        return fail(PL_EDEVICE, "%s: LDS of %zu bytes refused", what, smem);
+    return PL_OK;
+}
+
+// Batched transforms of length f.n along a strided axis; the tables of f are
+// at `tables` (device).
+int run_fft(const float2* in, float2* out, const AxisFft& f, const char* tables, long long nbatch, int inner,
             long long in_so, long long in_si, long long in_sn, long long out_so, long long out_si,
-            long long out_sn, int sign, float scale, const Radices& rad, hipStream_t s,
-            const char* what) {
+            long long out_sn, int sign, float scale, hipStream_t s, const char* what) {
     FftArgs a{};
-    a.n = n;
+    a.n = f.n;
+    a.m = f.m;
     a.nbatch = static_cast<int>(nbatch);
     a.inner = inner;
-    a.per_wg = std::max(1, std::min(64, 2048 / n));
-    a.ld = n + 1;
+    a.per_wg = std::max(1, std::min(64, 2048 / f.m));
+    a.ld = f.m + 1;
     a.sign = sign;
     a.n_fast_in = in_sn == 1;
     a.n_fast_out = out_sn == 1;
@@ -241,13 +336,24 @@ int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nb
     a.out_sn = out_sn;
     a.scale = scale;
     a.inv_inner = 1.0f / inner;
-    a.rad = rad;
+    a.rad = f.rad;
     if (nbatch <= 0) return PL_OK;
     if (nbatch > (1LL << 31) - 1) return fail(PL_EUNSUPPORTED, "%s: too many transforms", what);
+    const float2* tw = reinterpret_cast<const float2*>(tables + f.off_tw);
+    if (f.chirp) {
+        const size_t smem = 2ull * a.per_wg * a.ld * sizeof(float2);
+        int rc = set_lds_limit(reinterpret_cast<const void*>(fft_chirp_strided_kernel), smem, what);
+        if (rc) return rc;
+        const long long blocks = (nbatch + a.per_wg - 1) / a.per_wg;
+        hipLaunchKernelGGL(fft_chirp_strided_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out,
+                           tw, reinterpret_cast<const float2*>(tables + f.off_chirp),
+                           reinterpret_cast<const float2*>(tables + f.off_hat), a);
+        return check_launch(what);
+    }
     // the wavefront kernel splits batch indices with a float reciprocal (exact
     // below 2^22)
-    if (n % 64 == 0 && nbatch + inner < (1LL << 21)) {
-        switch (n / 64) {
+    if (f.n % 64 == 0 && nbatch + inner < (1LL << 21)) {
+        switch (f.n / 64) {
             case 2: return launch_fft_wave<2>(a, in, out, tw, s, what);
             case 3: return launch_fft_wave<3>(a, in, out, tw, s, what);
             case 4: return launch_fft_wave<4>(a, in, out, tw, s, what);
@@ -258,6 +364,8 @@ int run_fft(const float2* in, float2* out, const float2* tw, int n, long long nb
         }
     }
     const size_t smem = 2ull * a.per_wg * a.ld * sizeof(float2);
+    int rc = set_lds_limit(reinterpret_cast<const void*>(fft_strided_kernel), smem, what);
+    if (rc) return rc;
     const long long blocks = (nbatch + a.per_wg - 1) / a.per_wg;
     hipLaunchKernelGGL(fft_strided_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out,
                        tw, a);
@@ -289,53 +397,62 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
         a.glw[q] = p.gl_w[q];
     }
     a.scan_step = p.scan_step;
-    const long long total = static_cast<long long>(p.n_ch) + p.n_z + p.n_fine + p.n_l +
+    const long long total = static_cast<long long>(p.n_ch) + p.n_fine + p.n_l +
                             static_cast<long long>(p.n_z) * p.n_f;
     const int blocks = static_cast<int>(std::min<long long>((total + 255) / 256, 4096));
     hipLaunchKernelGGL(plan_tables_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan, dt.k,
                        reinterpret_cast<double*>(ws + p.off_llo), reinterpret_cast<double*>(ws + p.off_lref),
-                       reinterpret_cast<float2*>(ws + p.off_tw_scan),
                        reinterpret_cast<float2*>(ws + p.off_tw_fine), reinterpret_cast<float*>(ws + p.off_deap),
                        reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk));
-    const int rc = check_launch("plan tables");
+    int rc = check_launch("plan tables");
+    if (!rc) rc = launch_axis_fft_tables(p.zfft, ws + p.off_zfft, s);
     return rc ? rc : launch_gather_tables(p, dt, ws, s);
 }
 
-int launch_twiddles(float2* tw, int n, hipStream_t s) {
-    hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
-    return check_launch("twiddles");
+int launch_axis_fft_tables(const AxisFft& f, char* tables, hipStream_t s) {
+    const int total = f.m + (f.chirp ? f.n + f.m : 0);
+    hipLaunchKernelGGL(axis_fft_tables_kernel, dim3((total + 255) / 256), dim3(256), 0, s, f.n, f.m, f.chirp ? 1 : 0,
+                       reinterpret_cast<float2*>(tables + f.off_tw), reinterpret_cast<float2*>(tables + f.off_chirp),
+                       reinterpret_cast<float2*>(tables + f.off_pad));
+    int rc = check_launch("transform tables");
+    if (rc || !f.chirp) return rc;
+    // hat = FFT_m(pad) / m: one smooth transform of length m
+    AxisFft g = f;
+    g.n = f.m;
+    g.chirp = false;
+    return run_fft(reinterpret_cast<const float2*>(tables + f.off_pad), reinterpret_cast<float2*>(tables + f.off_hat), g,
+                   tables, 1, 1, 0, 0, 1, 0, 0, 1, -1, 1.0f / f.m, s, "transform tables (chirp filter)");
 }
 
 // s[c][m][f] -> S[c][kz][f]: forward transform over m (stride n_f).
-int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const float2* tw,
-                    const Radices& rad, hipStream_t s) {
+int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const AxisFft& f, const char* tables,
+                    hipStream_t s) {
     const long long nf = g->n_freq, nz = g->n_scan;
-    return run_fft(echo, spec, tw, g->n_scan, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf,
-                   nz * nf, 1, nf, -1, 1.0f, rad, s, "scan fft");
+    return run_fft(echo, spec, f, tables, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf, nz * nf, 1,
+                   nf, -1, 1.0f, s, "scan fft");
 }
 
 // G[p][kz] -> g[z][p]: inverse transform over k_z with 1/n_z.
-int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const float2* tw, hipStream_t s) {
+int launch_kz_ifft(const HybridPlan& p, const float2* G, float2* image, const char* tables, hipStream_t s) {
     const long long npix = static_cast<long long>(p.nx) * p.ny;
-    return run_fft(G, image, tw, p.n_z, npix, 1, p.n_z, 0, 1, 1, 0, npix, +1, 1.0f / p.n_z, p.scan_rad, s,
-                   "kz ifft");
+    return run_fft(G, image, p.zfft, tables, npix, 1, p.n_z, 0, 1, 1, 0, npix, +1, 1.0f / p.n_z, s, "kz ifft");
 }
 
 // g[z][p] -> G~[p][kz]: adjoint of launch_kz_ifft (forward transform over z
 // with 1/n_z).
-int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const float2* tw, hipStream_t s) {
+int launch_kz_fft_adjoint(const HybridPlan& p, const float2* image, float2* Gt, const char* tables, hipStream_t s) {
     const long long npix = static_cast<long long>(p.nx) * p.ny;
-    return run_fft(image, Gt, tw, p.n_z, npix, 1, 1, 0, npix, p.n_z, 0, 1, -1, 1.0f / p.n_z, p.scan_rad, s,
+    return run_fft(image, Gt, p.zfft, tables, npix, 1, 1, 0, npix, p.n_z, 0, 1, -1, 1.0f / p.n_z, s,
                    "kz fft (adjoint)");
 }
 
 // S~[c][kz][f] -> s~[c][m][f]: adjoint of launch_scan_fft (unnormalised
 // inverse transform over kz).
-int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const float2* tw,
-                            const Radices& rad, hipStream_t s) {
+int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo, const AxisFft& f,
+                            const char* tables, hipStream_t s) {
     const long long nf = g->n_freq, nz = g->n_scan;
-    return run_fft(St, echo, tw, g->n_scan, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf,
-                   nz * nf, 1, nf, +1, 1.0f, rad, s, "scan fft (adjoint)");
+    return run_fft(St, echo, f, tables, static_cast<long long>(g->n_ch) * nf, g->n_freq, nz * nf, 1, nf, nz * nf, 1,
+                   nf, +1, 1.0f, s, "scan fft (adjoint)");
 }
 
 }  // namespace pl

@@ -98,8 +98,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         return fail(PL_EINVAL, "unknown interpolation %d", p.interp);
     if (!(p.sigma_l >= 2.0 && p.sigma_l <= 64.0)) return fail(PL_EINVAL, "l_oversample must be in [2, 64]");
     if (!(p.tol >= 1e-12 && p.tol <= 1e-2)) return fail(PL_EINVAL, "nufft_tol must be in [1e-12, 1e-2]");
-    if (!factor_radices(p.n_z, &p.scan_rad))
-        return fail(PL_EUNSUPPORTED, "n_scan = %d is not a product of 2, 3 and 5", p.n_z);
+    if (int rc = plan_axis_fft(p.n_z, &p.zfft)) return rc;
 
     // Dispersion k_rho = sqrt(k^2 - k_z^2 / 4) for the range l = rho_T + rho_R
     // (eq. 18; the monostatic eq. 5 is the same relation with l = 2 rho).
@@ -109,8 +108,8 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // Reference wavenumber of every k_z block and the range-grid step for a
     // given block size.
     auto set_blocks = [&](int block, double sigma) {
-        p.block = block;
-        p.n_blocks = (p.n_z + p.block - 1) / p.block;
+        p.block = std::max(block, kMinBlock);
+        p.n_blocks = (p.n_z + p.block - 1) / p.block;  // <= kMaxScan / kMinBlock = kMaxBlocks
         double half_band = 0.0;
         for (int b = 0; b < p.n_blocks; ++b) {
             double lo = 1e300, hi = -1e300;
@@ -357,7 +356,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_G = take(npix * nz * 8);
     p.off_llo = take(nch * 8);
     p.off_lref = take(nch * 8);
-    p.off_tw_scan = take(nz * 8);
+    p.off_zfft = take(p.zfft.bytes);
     p.off_tw_fine = take(static_cast<size_t>(p.n_fine) * 8);
     p.off_deap = take(static_cast<size_t>(p.n_l) * 4);
     p.off_kp = take(nz * nf * 8);

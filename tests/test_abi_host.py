@@ -112,12 +112,38 @@ def test_plan_errors():
     with pytest.raises(pr.PolyreconError) as e:
         pr.hybrid_plan_info(g, W.C1.grid, nufft_tol=0.5)
     assert e.value.code == pr.PL_EINVAL
-    g7 = pr.make_geometry(replace(W.C1.array, n_scan=7))     # no radix-7 FFT
-    with pytest.raises(pr.PolyreconError) as e:
-        pr.hybrid_plan_info(g7, W.C1.grid)
-    assert e.value.code == pr.PL_EUNSUPPORTED
     with pytest.raises(ValueError):
         pr.hybrid_plan_info(g, W.C1.grid, precision="fp64")
+
+
+def _smooth(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@pytest.mark.parametrize("n_scan", [7, 131, 509, 2304, 2310, 4096, 4093])
+def test_plan_blocks_and_transform_length_at_any_scan_length(n_scan):
+    # Every k_z block gets its band-centre reference wavenumber, also past
+    # 64 blocks (scans longer than 2048 with 32-bin blocks), and the scan
+    # transform runs through n_scan itself when it is 2,3,5-smooth, else
+    # through the smallest smooth length >= 2 n_scan - 1 (chirp-z).
+    a = replace(W.C1.array, n_scan=n_scan)
+    g = pr.make_geometry(a)
+    for opts in ({}, dict(kz_per_lane=1)):
+        p = pr.hybrid_plan_info(g, W.C1.grid, **opts)
+        assert p.n_blocks == -(-n_scan // p.block) and len(p.k_ref) == p.n_blocks
+        kz = 2 * np.pi * np.fft.fftfreq(n_scan, a.scan_step)
+        kf = 2 * np.pi * np.linspace(a.f_start, a.f_stop, a.n_freq) / W.SPEED_OF_LIGHT
+        for b in range(p.n_blocks):
+            kr2 = kf[None] ** 2 - kz[b * p.block:(b + 1) * p.block, None] ** 2 / 4
+            kr = np.sqrt(kr2[kr2 > 0])
+            want = 0.5 * (kr.min() + kr.max()) if kr.size else 0.0
+            assert math.isclose(p.k_ref[b], want, rel_tol=1e-12, abs_tol=1e-9)
+        want_len = n_scan if _smooth(n_scan) else min(m for m in range(2 * n_scan - 1, 4 * n_scan) if _smooth(m))
+        assert p.scan_fft_len == want_len
+    assert pr.fft_workspace_bytes(g) >= 8 * want_len * (1 if _smooth(n_scan) else 3)
 
 
 def test_sampling_criteria():
@@ -154,7 +180,11 @@ def test_raw_abi_argument_errors_before_device_use():
     assert L.reconstruct_bp(g.handle, grid, 0, 1, fake, fake, fake, 16, None) == pr.PL_EWORKSPACE
     assert L.simulate_echo(g.handle, -1, fake, fake, fake, None) == pr.PL_EINVAL
     assert L.simulate_echo(g.handle, 3, None, fake, fake, None) == pr.PL_EINVAL
-    assert L.scan_fft(None, fake, fake, None) == pr.PL_EINVAL
+    assert L.scan_fft(None, fake, fake, fake, 1 << 20, None) == pr.PL_EINVAL
+    fneed = pr.fft_workspace_bytes(g)
+    assert L.scan_fft(g.handle, fake, fake, None, fneed, None) == pr.PL_EWORKSPACE
+    assert L.scan_fft(g.handle, fake, fake, fake, fneed - 1, None) == pr.PL_EWORKSPACE
+    assert L.kz_ifft(g.handle, grid, fake, fake, C.c_void_p((1 << 20) + 8), fneed, None) == pr.PL_EWORKSPACE
 
 
 def _fine_grid(nx, ny, d):

@@ -81,11 +81,13 @@ def multi_small():
 
 
 # ------------------------------------------------------------------ FFTs
-@pytest.mark.parametrize("n_scan", [10, 24, 128, 192, 256, 320, 384, 512])
+@pytest.mark.parametrize("n_scan", [1, 7, 10, 24, 127, 128, 131, 192, 251, 256, 320, 384, 448, 509, 512, 2310, 4093])
 def test_scan_fft_and_kz_ifft(n_scan):
-    # 64 R points (R = 2, 3, 4, 5, 6, 8) take the wavefront FFT, the others
-    # the Stockham stages; 9 frequencies and 15 pixels leave partial
-    # workgroups and transforms that straddle channels
+    # 64 R points (R = 2, 3, 4, 5, 6, 8) take the wavefront FFT, other
+    # 2,3,5-smooth lengths the Stockham stages, the rest (primes, 7 | n) the
+    # chirp-z transform (4093: through 8192 points, one transform per
+    # workgroup); 9 frequencies and 15 pixels leave partial workgroups and
+    # transforms that straddle channels
     a = replace(W.tiny("mono").array, n_scan=n_scan, n_freq=9)
     g = pr.make_geometry(a)
     say("scan_fft", n_scan)
@@ -428,6 +430,23 @@ def test_valu_backprojection_kernels(case, kernel):
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("case,n_scan", [("C1", 131), ("C1", 37), ("multi-small", 53), ("tiny-mono", 1)])
+def test_hybrid_scan_lengths_that_are_not_smooth(case, n_scan):
+    # eqs. (2), (9) and (12) hold for any number of scan positions: prime
+    # lengths, 7 | n and a single position, end to end against the oracle
+    base = {"C1": W.C1, "multi-small": multi_small(), "tiny-mono": W.tiny("mono")}[case]
+    wl = replace(base, array=replace(base.array, n_scan=n_scan))
+    g = pr.make_geometry(wl.array)
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 17)
+    plan = pr.hybrid_plan_info(g, wl.grid)
+    say("scan length", case, n_scan, "transform length", plan.scan_fft_len)
+    img = host(pr.reconstruct_hybrid(g, wl.grid, dev(s)))
+    err = rel(img, ohyb.image(arr, wl.grid, s))
+    say("   rel L2", err)
+    assert err < 1e-4
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (9, 13), (17, 5), (64, 40)])
 def test_hybrid_ragged_grids(nx, ny):
     wl = W.tiny("multi")
@@ -486,9 +505,11 @@ def _spectrum_subset(img, kappas, pix):
 
 @pytest.mark.parametrize("wl,precision,mfma_bp", [(W.C2, "fp32", 0), (W.C3, "fp32", 0), (W.C2, "bf16", 0),
                                                  (W.C2, "fp16", 0), (W.C3, "bf16", 0), (W.C2, "bf16", 1),
-                                                 (W.C2, "fp16", 1), (W.C3, "bf16", 1)],
+                                                 (W.C2, "fp16", 1), (W.C3, "bf16", 1), (W.C2, "fp16", 2),
+                                                 (W.C3, "fp16", 2)],
                          ids=["C2-fp32", "C3-fp32", "C2-bf16", "C2-fp16", "C3-bf16", "C2-bf16-mfma-bp",
-                              "C2-fp16-mfma-bp", "C3-bf16-mfma-bp"])
+                              "C2-fp16-mfma-bp", "C3-bf16-mfma-bp", "C2-fp16-mfma-bp-1pass",
+                              "C3-fp16-mfma-bp-1pass"])
 def test_hybrid_full_size_sampled(wl, precision, mfma_bp):
     # The full workload in the launch configuration the benchmark times;
     # the oracle evaluates sampled (k_z, pixel) pairs of the spectrum.

@@ -155,27 +155,19 @@ C3 = Workload(
 
 WORKLOADS = {"C1": C1, "C2": C2, "C3": C3}
 
-def _is_smooth(n: int) -> bool:
-    for p in (2, 3, 5):
-        while n % p == 0:
-            n //= p
-    return n == 1
-
-
 def batch_c5(n_scans: int = 16, first_seed: int = 50):
     """The uneven batch: monostatic scans on R = 0.6 m with 4.408 mm elements
     and 4 mm scan steps, each with its own chord count (3-7), elements per
-    chord (32-64), scan length (a 2,3,5-smooth number in 128-512) and
-    frequency count (32-128, 26-34 GHz), drawn from numpy's default_rng(seed)
-    for seeds first_seed, first_seed + 1, ...; 1000 shell scatterers with the
-    z semi-axis 0.45 x the scan length; images 128 x 128 over 0.60 m."""
-    smooth = [n for n in range(128, 513) if _is_smooth(n)]
+    chord (32-64), scan length (any integer in 128-512) and frequency count
+    (32-128, 26-34 GHz), drawn from numpy's default_rng(seed) for seeds
+    first_seed, first_seed + 1, ...; 1000 shell scatterers with the z
+    semi-axis 0.45 x the scan length; images 128 x 128 over 0.60 m."""
     out = []
     for seed in range(first_seed, first_seed + n_scans):
         rng = np.random.default_rng(seed)
         n_chords = int(rng.integers(3, 8))
         n_elem = int(rng.integers(32, 65))
-        n_scan = int(rng.choice(smooth))
+        n_scan = int(rng.integers(128, 513))
         n_freq = int(rng.integers(32, 129))
         arr = ArrayDesc(mode="mono", n_chords=n_chords, radius=0.6, n_elem=n_elem, spacing=_D_MONO,
                         n_scan=n_scan, scan_step=0.004, n_freq=n_freq, f_start=26e9, f_stop=34e9)
