@@ -42,7 +42,11 @@ def scan_spectrum(echo):
 
 
 def kz_grid(n_scan, scan_step):
-    """Spatial frequencies of the scan axis in rad/m, numpy FFT order."""
+    """Spatial frequencies of the scan axis in rad/m, numpy FFT order.  A
+    single scan position has the one frequency k_z = 0 (a DFT of length 1),
+    whatever the step."""
+    if n_scan == 1:
+        return np.zeros(1)
     return 2.0 * np.pi * np.fft.fftfreq(n_scan, d=scan_step)
 
 

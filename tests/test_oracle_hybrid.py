@@ -271,6 +271,23 @@ def test_multistatic_image_matches_bp_shape():
     assert np.corrcoef(a[focal], b[focal])[0, 1] > 0.95
 
 
+@pytest.mark.parametrize("mode", ["mono", "multi"])
+def test_single_scan_position_is_bp_on_the_scan_plane(mode):
+    # One scan position: the only spatial frequency is k_z = 0, where (5)
+    # and (18) give k_rho = 2k (mono) and k (multi, range rho_T + rho_R);
+    # on the plane of the scan the 3-D distances equal the horizontal ones,
+    # so the hybrid image is exactly the brute-force BP sum there.
+    from oracle import bp
+    wl = W.tiny(mode)
+    arr = geometry.build(replace(wl.array, n_scan=1))
+    rng = np.random.default_rng(9)
+    s = W.complex_normal(rng, arr_echo_shape(arr))
+    gh = hybrid.image(arr, wl.grid, s)
+    gb = bp.bp_image(arr, wl.grid, s, z_index=[0])
+    assert gh.shape == gb.shape == (1, wl.grid.ny, wl.grid.nx)
+    assert np.linalg.norm(gh - gb) <= 1e-12 * np.linalg.norm(gb)
+
+
 def test_image_adjoint_dot_product():
     # <H s, g> = <s, H^H g> for random echo and image (inner products in the
     # complex128 sense, conjugate on the first argument)
