@@ -105,8 +105,9 @@ typedef struct pl_geometry_info {
 } pl_geometry_info;
 
 /*
- * Build a polyline array (Sec. II-A/B).  Host-only work; device tables are
- * uploaded lazily on the first device call on each device.
+ * Build a polyline array (Sec. II-A/B).  Host-only work: the small device
+ * tables (channel positions, wavenumbers) are uploaded by geometry_upload,
+ * or on the first device call on a device that has none.
  * Errors: PL_EINVAL (null pointers, non-positive sizes, f_start >= f_stop,
  * n_scan < 1, n_scan > 4096, n_freq > 1024, bad n_tx), PL_EGEOM (chord length
  * n_elem * spacing >= 2 R_0).  *out is left untouched on failure.
@@ -115,6 +116,19 @@ int make_geometry(const pl_geometry_desc* desc, pl_geometry** out);
 
 /* Release a handle (NULL is accepted).  Frees its device tables. */
 int destroy_geometry(pl_geometry* geom);
+
+/*
+ * Copy the geometry's device tables (channel Tx/Rx positions, float64
+ * [n_channels][4]; wavenumbers, float64 [n_freq]) to the current device:
+ * two small allocations and two stream-ordered copies on `stream`.  Call it
+ * once per device before capturing work into a graph or timing the first
+ * call: with the tables present, no reconstruction, simulation or transform
+ * call allocates or synchronises.  A device call on a device without them
+ * uploads them itself (allocating) the first time.  Idempotent; the tables
+ * are freed by destroy_geometry.
+ * Errors: PL_EINVAL (null geometry), PL_EDEVICE.
+ */
+int geometry_upload(const pl_geometry* geom, hipStream_t stream);
 
 /*
  * Describe a geometry.  Any of the host arrays may be NULL; otherwise they

@@ -77,6 +77,7 @@ _P = C.c_void_p
 _SIGNATURES = {
     "make_geometry": (C.c_int, [C.POINTER(GeometryDesc), C.POINTER(_P)]),
     "destroy_geometry": (C.c_int, [_P]),
+    "geometry_upload": (C.c_int, [_P, _P]),
     "geometry_info": (C.c_int, [_P, C.POINTER(GeometryInfo), _P, _P, _P, _P, _P]),
     "check_sampling": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(C.c_uint32)]),
     "simulate_echo": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
@@ -169,6 +170,10 @@ class Geometry:
         h = _P()
         _check(lib().make_geometry(C.byref(d), C.byref(h)))
         self.handle = h
+        if _torch().cuda.is_available():
+            # the device tables on the current device, stream-ordered: later
+            # calls then allocate nothing (graph capture, timing)
+            _check(lib().geometry_upload(h, _stream()))
         info = GeometryInfo()
         _check(lib().geometry_info(h, C.byref(info), None, None, None, None, None))
         self.mode = "mono" if info.mode == PL_MONO else "multi"

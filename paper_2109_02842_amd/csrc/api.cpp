@@ -14,7 +14,8 @@ bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) 
 // which only the VALU back-projection reads; they plan without the
 // matrix-core back-projection.
 int prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws, size_t ws_bytes,
-            HybridPlan* p, DeviceTables* dt, const char* what, bool stage = false) {
+            HybridPlan* p, DeviceTables* dt, const char* what, hipStream_t stream, bool stage = false,
+            bool upload = true) {
     pl_hybrid_opts o{};
     if (opts) o = *opts;
     if (stage) {
@@ -28,7 +29,7 @@ int prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opt
     if (!aligned256(ws)) return fail(PL_EWORKSPACE, "%s: workspace must be 256-byte aligned", what);
     if (ws_bytes < p->total)
         return fail(PL_EWORKSPACE, "%s: workspace of %zu bytes, %zu needed", what, ws_bytes, p->total);
-    return g->device_tables(dt);
+    return g->device_tables(dt, stream, upload);
 }
 
 // The standalone transform calls: the tables of the length-n_scan transform
@@ -98,7 +99,7 @@ int simulate_echo(const pl_geometry* g, int32_t n_scat, const double* xyz, const
     if (n_scat < 0) return fail(PL_EINVAL, "simulate_echo: n_scat < 0");
     if (n_scat > 0 && (!xyz || !refl)) return fail(PL_EINVAL, "simulate_echo: null scatterer arrays");
     DeviceTables dt;
-    int rc = g->device_tables(&dt);
+    int rc = g->device_tables(&dt, stream);
     if (rc) return rc;
     return launch_simulate(g, dt, n_scat, xyz, refl, reinterpret_cast<float2*>(echo), stream);
 }
@@ -132,7 +133,7 @@ int range_compress(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     if (!spec || !q) return fail(PL_EINVAL, "range_compress: null pointer");
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "range_compress", true);
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "range_compress", stream, true);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
@@ -156,7 +157,7 @@ int backproject(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid
     if (!q || !spectrum) return fail(PL_EINVAL, "backproject: null pointer");
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "backproject", true);
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "backproject", stream, true);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
     if ((rc = launch_plan_tables(p, dt, w, stream))) return rc;
@@ -182,21 +183,21 @@ int kz_ifft(const pl_geometry* g, const pl_image_grid* grid, const float* spectr
 }  // extern "C"
 
 namespace pl {
-namespace {
 
 // The hybrid reconstruction; tables = false skips the plan-table step (the
 // caller prepared the workspace with hybrid_prepare for the same arguments).
 int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
-                     float* image, void* ws, size_t ws_bytes, hipEvent_t* ev, hipStream_t stream, bool tables) {
+                     float* image, void* ws, size_t ws_bytes, hipEvent_t* ev, hipStream_t stream, bool tables,
+                     bool upload, const char* what) {
     clear_error();
-    if (!echo || !image) return fail(PL_EINVAL, "reconstruct_hybrid: null echo or image");
+    if (!echo || !image) return fail(PL_EINVAL, "%s: null echo or image", what);
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "reconstruct_hybrid");
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, what, stream, false, upload);
     if (rc) return rc;
     auto mark = [&](int i) -> int {
         if (ev && ev[i] && hipEventRecord(ev[i], stream) != hipSuccess)
-            return fail(PL_EDEVICE, "reconstruct_hybrid: hipEventRecord failed");
+            return fail(PL_EDEVICE, "%s: hipEventRecord failed", what);
         return PL_OK;
     };
     char* w = static_cast<char*>(ws);
@@ -223,7 +224,6 @@ int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_h
     return mark(5);
 }
 
-}  // namespace
 }  // namespace pl
 
 extern "C" {
@@ -231,12 +231,14 @@ extern "C" {
 int reconstruct_hybrid_events(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
                               const float* echo, float* image, void* ws, size_t ws_bytes, hipEvent_t* ev,
                               hipStream_t stream) {
-    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, ev, stream, true);
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, ev, stream, true, true,
+                                "reconstruct_hybrid_events");
 }
 
 int reconstruct_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
                        float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
-    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, true);
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, true, true,
+                                "reconstruct_hybrid");
 }
 
 int hybrid_prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, void* ws,
@@ -245,14 +247,15 @@ int hybrid_prepare(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     clear_error();
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "hybrid_prepare");
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "hybrid_prepare", stream);
     if (rc) return rc;
     return launch_plan_tables(p, dt, static_cast<char*>(ws), stream);
 }
 
 int reconstruct_hybrid_prepared(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
                                 const float* echo, float* image, void* ws, size_t ws_bytes, hipStream_t stream) {
-    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, false);
+    return pl::reconstruct_impl(g, grid, opts, echo, image, ws, ws_bytes, nullptr, stream, false, true,
+                                "reconstruct_hybrid_prepared");
 }
 
 int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* image,
@@ -262,7 +265,7 @@ int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     if (!image || !echo) return fail(PL_EINVAL, "adjoint_hybrid: null image or echo");
     HybridPlan p;
     DeviceTables dt;
-    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "adjoint_hybrid");
+    int rc = prepare(g, grid, opts, ws, ws_bytes, &p, &dt, "adjoint_hybrid", stream);
     if (rc) return rc;
     if (p.precision != PL_PREC_FP32 || !p.bp_gather)
         return fail(PL_EUNSUPPORTED, "adjoint_hybrid: needs the FP32 plan with the pixel-per-lane back-projection");
@@ -299,7 +302,7 @@ int reconstruct_bp(const pl_geometry* g, const pl_image_grid* grid, int32_t iz0,
     const size_t need = static_cast<size_t>(g->n_ch) * g->n_scan * g->n_freq * 8;
     if (!ws || ws_bytes < need) return fail(PL_EWORKSPACE, "reconstruct_bp: workspace of %zu bytes, %zu needed", ws_bytes, need);
     DeviceTables dt;
-    int rc = g->device_tables(&dt);
+    int rc = g->device_tables(&dt, stream);
     if (rc) return rc;
     return launch_bp(g, dt, grid, iz0, nz, reinterpret_cast<const float2*>(echo), static_cast<float2*>(ws),
                      reinterpret_cast<float2*>(image), stream);

@@ -193,7 +193,7 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoe
     std::vector<DeviceTables> dts(n);
     int rc = PL_OK;
     for (int s = 0; s < n; ++s)
-        if ((rc = b->geoms[s]->device_tables(&dts[s]))) return rc;
+        if ((rc = b->geoms[s]->device_tables(&dts[s], stream))) return rc;
 
     // plan tables, scan FFT, range compression per scan
     for (int s = 0; s < n; ++s) {

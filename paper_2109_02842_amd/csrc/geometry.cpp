@@ -81,7 +81,7 @@ int plan_axis_fft(int n, AxisFft* out) {
 
 }  // namespace pl
 
-int pl_geometry::device_tables(pl::DeviceTables* out) const {
+int pl_geometry::device_tables(pl::DeviceTables* out, hipStream_t stream, bool upload) const {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return pl::fail(PL_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
@@ -91,18 +91,14 @@ int pl_geometry::device_tables(pl::DeviceTables* out) const {
         *out = it->second;
         return PL_OK;
     }
+    if (!upload)
+        return pl::fail(PL_EINVAL, "the geometry's tables are not on device %d (geometry_upload first)", dev);
     pl::DeviceTables t;
-    std::vector<double> chan(static_cast<size_t>(n_ch) * 4);
-    for (int c = 0; c < n_ch; ++c) {
-        chan[4 * c + 0] = tx[2 * c];
-        chan[4 * c + 1] = tx[2 * c + 1];
-        chan[4 * c + 2] = rx[2 * c];
-        chan[4 * c + 3] = rx[2 * c + 1];
-    }
     e = hipMalloc(&t.chan, chan.size() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&t.k, k.size() * sizeof(double));
-    if (e == hipSuccess) e = hipMemcpy(t.chan, chan.data(), chan.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t.k, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t.chan, chan.data(), chan.size() * sizeof(double), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.k, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) {
         if (t.chan) (void)hipFree(t.chan);
         if (t.k) (void)hipFree(t.k);
@@ -231,8 +227,22 @@ int make_geometry(const pl_geometry_desc* d, pl_geometry** out) {
         g->f[i] = (i == d->n_freq - 1 && d->n_freq > 1) ? d->f_stop_hz : d->f_start_hz + i * df;
         g->k[i] = 2.0 * kPi * g->f[i] / kSpeedOfLight;
     }
+    g->chan.resize(static_cast<size_t>(g->n_ch) * 4);
+    for (int c = 0; c < g->n_ch; ++c) {
+        g->chan[4 * c + 0] = g->tx[2 * c];
+        g->chan[4 * c + 1] = g->tx[2 * c + 1];
+        g->chan[4 * c + 2] = g->rx[2 * c];
+        g->chan[4 * c + 3] = g->rx[2 * c + 1];
+    }
     *out = g;
     return PL_OK;
+}
+
+int geometry_upload(const pl_geometry* g, hipStream_t stream) {
+    pl::clear_error();
+    if (!g) return pl::fail(PL_EINVAL, "geometry_upload: null geometry");
+    pl::DeviceTables dt;
+    return g->device_tables(&dt, stream, true);
 }
 
 int destroy_geometry(pl_geometry* g) {

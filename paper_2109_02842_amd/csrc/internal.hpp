@@ -80,11 +80,15 @@ struct pl_geometry {
     std::vector<double> tx, rx;          // [n_ch][2]
     std::vector<double> z, f, k;         // scan heights, frequencies, wavenumbers
     std::vector<double> ends;            // [n_chords][2][2]
+    std::vector<double> chan;            // [n_ch][4]: x_T, y_T, x_R, y_R (source of the device copy)
     mutable std::mutex mu;
     mutable std::map<int, pl::DeviceTables> dev;
 
-    // Device tables for the current device (uploaded on first use).
-    int device_tables(pl::DeviceTables* out) const;
+    // Device tables for the current device.  If there are none yet and
+    // upload is true they are allocated and copied in stream order on
+    // `stream` (the copies read chan and k, which live as long as the
+    // handle); with upload false that is an error (PL_EINVAL).
+    int device_tables(pl::DeviceTables* out, hipStream_t stream = nullptr, bool upload = true) const;
     ~pl_geometry();
 };
 
@@ -143,6 +147,15 @@ int launch_gather_batch(const void* descs, const void* items, const int* bounds,
                         int kb, int rsc, size_t smem, int blocks, hipStream_t s);
 int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts,
               HybridPlan* p);
+
+// The hybrid reconstruction (reconstruct_hybrid and its variants): tables =
+// false skips the plan-table step (ws prepared by hybrid_prepare); upload =
+// false takes the geometry's device tables as already uploaded (no
+// allocation; PL_EINVAL if they are not); what names the entry point in
+// error messages; ev: optional stage events.
+int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_opts* opts, const float* echo,
+                     float* image, void* ws, size_t ws_bytes, hipEvent_t* ev, hipStream_t stream, bool tables,
+                     bool upload, const char* what);
 
 // ---------------------------------------------------------- launchers
 int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
