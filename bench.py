@@ -27,6 +27,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0               # MI355X published HBM3E bandwidth
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X published dense BF16 matrix peak
 FLOP_PER_TERM = 24                  # (8 + 4P) with P = 4 interpolation taps
+CPU_SHARE_THREADS = 16              # host threads that come with one GPU
 
 
 def stage_rooflines(plan, a, wl, geom, stage, args):
@@ -111,7 +112,10 @@ def cpu_baseline(wl, echo_np, budget_s=20.0):
     npix = wl.grid.nx * wl.grid.ny
     px, py = ohyb.pixel_grid(wl.grid)
     S = ohyb.scan_spectrum(echo_np)   # the FFTs: negligible next to the sums
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    visible = len(os.sched_getaffinity(0))
+    # the CPU share that comes with one GPU is 16 threads (the host may show
+    # more cores, shared with the other GPUs' jobs); never more than visible
+    threads = max(1, min(CPU_SHARE_THREADS, visible))
 
     def run(pix, kap):
         chunks = [c for c in np.array_split(pix, threads) if c.size]
@@ -137,7 +141,8 @@ def cpu_baseline(wl, echo_np, budget_s=20.0):
     total_pairs = wl.array.n_scan * npix
     t_full = dt * total_pairs / pairs
     vox = npix * wl.array.n_scan
-    return {"value": vox / t_full, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+    return {"value": vox / t_full, "unit": "voxels/s", "cores": threads, "host_cpus_visible": visible,
+            "kind": "oracle",
             "sample": (f"exact spectrum (eq. 7 direct sums) at {pairs} (k_z, pixel) pairs of "
                        f"{total_pairs}, {dt:.1f} s on {threads} host threads, extrapolated linearly; "
                        f"scan FFTs excluded")}
@@ -166,72 +171,10 @@ def peak_error(pr, torch, W, wl, geom, opts):
     return worst
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C5"],
-                    help="C5: the uneven 16-scan batch (one call, graph-replayed)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-bp", action="store_true")
-    ap.add_argument("--bp-planes", type=int, default=2)
-    ap.add_argument("--tile", type=int, default=0, help="back-projection tile (0 = automatic)")
-    ap.add_argument("--interp", default="bspline4", choices=["bspline4", "lagrange4", "linear"])
-    ap.add_argument("--l-oversample", type=float, default=6.0)
-    ap.add_argument("--kz-per-lane", type=int, default=0)
-    ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1, 2],
-                    help="1: back-projection on the matrix cores (BF16/FP16 modes); 2: its single-pass FP16 form")
-    ap.add_argument("--tile-y", type=int, default=0)
-    ap.add_argument("--kz-block", type=int, default=0)
-    ap.add_argument("--range-method", default="nufft", choices=["nufft", "resample"],
-                    help="range compression: NUFFT (the paper's method) or uniform-grid resampling + IFFT")
-    ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the reconstruction is not sharded across GPUs)", flush=True)
-        return 2
-
-    import torch
-    import paper_2109_02842_amd as pr
-    import workloads as W
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", flush=True)
-        return 1
-    torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        n = args.calibrate_copy << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": n}), flush=True)
-        return 0
-    if args.config == "C5":
-        return bench_batch(args, torch, pr, W)
-    wl = W.WORKLOADS[args.config]
+def make_timers(pr, torch, W, wl, geom, echo, img):
+    """time_path(opts, steps, warmup) and parity(opts) for one workload
+    whose echo and image buffers are resident on the device."""
     a = wl.array
-    log(f"[bench] {args.config}: {describe(wl)}")
-    geom = pr.make_geometry(a)
-    pos, refl = W.scatterers(wl.scene)
-    echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
-    torch.cuda.synchronize()
-    opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
-                l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves,
-                mfma_backprojection=args.mfma_bp, tile_y=args.tile_y, kz_block=args.kz_block,
-                range_method=args.range_method)
-    plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
-    img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
-    log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
-        f"tile={plan.tile} du={plan.du * 1e3:.3f} mm workspace={plan.workspace_bytes / 2**20:.1f} MiB")
 
     def time_path(opts, steps, warmup):
         plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
@@ -298,6 +241,112 @@ def main() -> int:
             ref = ohyb.spectrum_at(arr, ohyb.scan_spectrum(s), kap, px[pix], py[pix])
         return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), f"{len(kap)} k_z x {pix.size} pixels"
 
+
+    return time_path, parity
+
+
+def bench_c3(args, torch, pr, W):
+    """The multistatic workload (C3) in the same run: the FP32 path and the
+    single-pass FP16 matrix-core path, each timed like the headline (plan
+    prepared once, inputs resident), with its error against the oracle on
+    sampled outputs and its peak-position error."""
+    wl = W.C3
+    a = wl.array
+    log(f"[bench] C3: {describe(wl)}")
+    geom = pr.make_geometry(a)
+    pos, refl = W.scatterers(wl.scene)
+    echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
+    img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    time_path, parity = make_timers(pr, torch, W, wl, geom, echo, img)
+    voxels = wl.grid.nx * wl.grid.ny * a.n_scan
+    res = {"workload": f"C3: {describe(wl)}"}
+    steps = max(1, min(args.steps, 5))
+    for name, opts in (("fp32", {}), ("fp16-mfma-bp-1pass", dict(precision="fp16", mfma_backprojection=2))):
+        ms, stage, _, med, plan = time_path(opts, steps, 2)
+        r = {"value": voxels / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": ms, "median_ms": med,
+             "steps": steps, "stages_ms": stage, "bp_kernel": plan.bp_kernel}
+        if not args.no_parity:
+            r["rel_l2_vs_oracle"], r["parity_sample"] = parity(opts)
+            r["peak_position_error_voxels"] = peak_error(pr, torch, W, wl, geom, opts)
+        res[name] = r
+        log(f"[bench] C3 {name}: {ms:.3f} ms/step ({voxels / (ms * 1e-3):.3e} voxels/s); "
+            f"rel L2 {r.get('rel_l2_vs_oracle', float('nan')):.2e}")
+    del echo, img
+    torch.cuda.empty_cache()
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2", choices=["C1", "C2", "C3", "C5"],
+                    help="C5: the uneven 16-scan batch (one call, graph-replayed)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bp", action="store_true")
+    ap.add_argument("--bp-planes", type=int, default=2)
+    ap.add_argument("--tile", type=int, default=0, help="back-projection tile (0 = automatic)")
+    ap.add_argument("--interp", default="bspline4", choices=["bspline4", "lagrange4", "linear"])
+    ap.add_argument("--l-oversample", type=float, default=6.0)
+    ap.add_argument("--kz-per-lane", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--mfma-bp", type=int, default=0, choices=[-1, 0, 1, 2],
+                    help="1: back-projection on the matrix cores (BF16/FP16 modes); 2: its single-pass FP16 form")
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--kz-block", type=int, default=0)
+    ap.add_argument("--range-method", default="nufft", choices=["nufft", "resample"],
+                    help="range compression: NUFFT (the paper's method) or uniform-grid resampling + IFFT")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the multistatic C3 block of the C2 run")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the reconstruction is not sharded across GPUs)", flush=True)
+        return 2
+
+    import torch
+    import paper_2109_02842_amd as pr
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", flush=True)
+        return 1
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return 0
+    if args.config == "C5":
+        return bench_batch(args, torch, pr, W)
+    wl = W.WORKLOADS[args.config]
+    a = wl.array
+    log(f"[bench] {args.config}: {describe(wl)}")
+    geom = pr.make_geometry(a)
+    pos, refl = W.scatterers(wl.scene)
+    echo = pr.simulate_echo(geom, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
+    torch.cuda.synchronize()
+    opts = dict(precision=args.precision, tile=args.tile, interp=args.interp,
+                l_oversample=args.l_oversample, kz_per_lane=args.kz_per_lane, waves=args.waves,
+                mfma_backprojection=args.mfma_bp, tile_y=args.tile_y, kz_block=args.kz_block,
+                range_method=args.range_method)
+    plan = pr.hybrid_plan_info(geom, wl.grid, **opts)
+    img = torch.empty((a.n_scan, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
+    log(f"[bench] plan: n_l={plan.n_l} n_fine={plan.n_fine} W={plan.kernel_width} window={plan.window} "
+        f"tile={plan.tile} du={plan.du * 1e3:.3f} mm workspace={plan.workspace_bytes / 2**20:.1f} MiB")
+
+    time_path, parity = make_timers(pr, torch, W, wl, geom, echo, img)
+
     ms, stage, first_ms, med_ms, plan = time_path(opts, args.steps, args.warmup)
     log(f"[bench] {args.precision}: {args.steps} steps {ms:.3f} ms/step (median {med_ms:.3f}); "
         + ", ".join(f"{k} {v:.3f}" for k, v in stage.items()))
@@ -357,9 +406,11 @@ def main() -> int:
                  "speedup_vs_main": ms / vms}
             if not args.no_parity:
                 v["rel_l2_vs_oracle"], _ = parity(vopts)
+                v["peak_position_error_voxels"] = peak_error(pr, torch, W, wl, geom, vopts)
             out["variants"][name] = v
             log(f"[bench] {name}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
-                f"backproject {vstage['backproject']:.3f} ms; rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}")
+                f"backproject {vstage['backproject']:.3f} ms; rel L2 {v.get('rel_l2_vs_oracle', float('nan')):.2e}; "
+                f"peak error {v.get('peak_position_error_voxels', float('nan')):.2f} voxels")
 
     if not args.no_variants:
         # the adjoint (image -> echo) of the FP32 pixel-per-lane plan: one
@@ -417,6 +468,9 @@ def main() -> int:
                 "omegaK_NUFFT_BP_ms": times["nufft"], "omegaK_BP_ms": times["resample"],
                 "BP_ms": voxels / bp_vps * 1e3,
                 "note": "whole volume, FP32; BP extrapolated from the timed slab"}
+
+    if args.config == "C2" and not args.no_c3:
+        out["multistatic_c3"] = bench_c3(args, torch, pr, W)
 
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")
