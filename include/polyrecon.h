@@ -340,6 +340,27 @@ int reconstruct_hybrid(const pl_geometry* geom, const pl_image_grid* grid,
                        void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * reconstruct_hybrid without a workspace argument and without any device
+ * allocation, for callers that cannot allocate: code under graph capture,
+ * tight serving loops, harnesses that forbid allocation.  The workspace is
+ * a static device array of PL_STATIC_SCRATCH_BYTES (64 MiB) per device,
+ * held from the library's first use on that device until the process ends
+ * (problems up to C1 size and somewhat beyond fit; hybrid_workspace_bytes
+ * tells).  The geometry's tables must be on the device already
+ * (geometry_upload); the call never uploads them.  Every call on a device
+ * shares that device's array and keeps nothing from the last call: calls
+ * that overlap on one device (other streams, other threads) race and must
+ * be serialised by the caller.  Same result as reconstruct_hybrid with the
+ * same arguments.
+ * Errors: PL_EINVAL (also: geometry not uploaded to this device),
+ * PL_EUNSUPPORTED, PL_EWORKSPACE (the problem's workspace exceeds
+ * PL_STATIC_SCRATCH_BYTES), PL_EDEVICE.
+ */
+#define PL_STATIC_SCRATCH_BYTES (64u << 20)
+int reconstruct_hybrid_static(const pl_geometry* geom, const pl_image_grid* grid, const pl_hybrid_opts* opts,
+                              const float* echo_dev, float* image_dev, hipStream_t stream);
+
+/*
  * Plan caching.  hybrid_prepare writes the plan's device tables (range-grid
  * origins, reference ranges, twiddles, deapodisation, k' and weight tables,
  * the back-projection's tile geometry) into ws; they depend on the geometry,

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "reconstruct_hybrid_prepared": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                                               C.c_size_t, _P]),
     "hybrid_prepare": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, C.c_size_t, _P]),
+    "reconstruct_hybrid_static": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P]),
     "adjoint_hybrid": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                                  C.c_size_t, _P]),
     "reconstruct_hybrid_events": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P,
@@ -368,6 +369,24 @@ def reconstruct_hybrid(geom: Geometry, grid, echo, out=None, ws=None, prepared=F
     _check(fn(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
               _dev_c64(echo, geom.echo_shape, "echo"), _dev_c64(out, shape, "out"),
               C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def reconstruct_hybrid_static(geom: Geometry, grid, echo, out=None, **opts):
+    """reconstruct_hybrid on the library's static per-device scratch: no
+    workspace and no device allocation inside the call (problems whose
+    workspace fits STATIC_SCRATCH_BYTES; calls on one device must not
+    overlap)."""
+    torch = _torch()
+    shape = (geom.n_scan, grid.ny, grid.nx)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=echo.device)
+    _check(lib().reconstruct_hybrid_static(geom.handle, C.byref(_grid(grid)), C.byref(_opts(**opts)),
+                                           _dev_c64(echo, geom.echo_shape, "echo"), _dev_c64(out, shape, "out"),
+                                           _stream()))
     return out
 
 

@@ -18,7 +18,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = "gfx950"
 
 SOURCES = ["geometry.cpp", "plan.cpp", "api.cpp", "batch.cpp", "k_fft.hip", "k_nufft.hip", "k_backproject.hip",
-           "k_simulate.hip", "k_mfma.hip", "k_backproject_mfma.hip", "k_adjoint.hip"]
+           "k_simulate.hip", "k_mfma.hip", "k_backproject_mfma.hip", "k_adjoint.hip", "static_ws.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-x", "hip",
