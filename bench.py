@@ -287,7 +287,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bp", action="store_true")
-    ap.add_argument("--bp-planes", type=int, default=2)
+    ap.add_argument("--bp-planes", type=int, default=4)
     ap.add_argument("--tile", type=int, default=0, help="back-projection tile (0 = automatic)")
     ap.add_argument("--interp", default="bspline4", choices=["bspline4", "lagrange4", "linear"])
     ap.add_argument("--l-oversample", type=float, default=6.0)
@@ -439,9 +439,9 @@ def main() -> int:
     if not args.no_bp:
         nz = max(1, min(args.bp_planes, a.n_scan))
         iz0 = a.n_scan // 2 - nz // 2
-        bws = pr.workspace(pr.bp_workspace_bytes(geom))
+        bws = pr.workspace(pr.bp_workspace_bytes(geom, wl.grid, nz))
         bimg = torch.empty((nz, wl.grid.ny, wl.grid.nx), dtype=torch.complex64, device="cuda")
-        pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=1, out=bimg[:1], ws=bws)
+        pr.reconstruct_bp(geom, wl.grid, echo, iz0=iz0, nz=nz, out=bimg, ws=bws)   # warm-up
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

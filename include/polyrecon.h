@@ -193,6 +193,10 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
 #define PL_RANGE_RESAMPLE 1 /* resampling onto a uniform k grid + inverse FFT     */
                             /* (the variant without NUFFT of Table 2), FP32 only  */
 
+/* Reference wavenumber k_ref of the range profiles (eq. 8a/8b, 19a/19b). */
+#define PL_REF_BAND_CENTRE 0 /* one per block of k_z bins: the centre of its k_rho band (default) */
+#define PL_REF_MIN_K 1       /* the paper's: per k_z, k_rho0 = k_rho at the lowest wavenumber    */
+
 /* Back-projection kernels (hybrid plan info). */
 #define PL_BP_KZ_LANES 0     /* VALU, one k_z bin per lane, weights broadcast */
 #define PL_BP_PIXEL_LANES 1  /* VALU, one pixel per lane, weights shared via LDS */
@@ -262,6 +266,25 @@ int simulate_echo(const pl_geometry* geom, int32_t n_scat, const double* xyz_dev
  *                 FP32 precision only (PL_EUNSUPPORTED otherwise), at least two
  *                 frequencies.  Its accuracy is that of the interpolation, not
  *                 the NUFFT tolerance.
+ *   ref_mode      reference wavenumber k_ref that demodulates the range
+ *                 profiles (eq. 8a/19a) and is restored by the carrier
+ *                 exp(j k_ref l) (eq. 8b/19b).  The two cancel exactly, so
+ *                 the choice changes only the profiles' bandwidth and with
+ *                 it the interpolation error.  PL_REF_BAND_CENTRE (default):
+ *                 one reference per block of k_z bins, the centre of the
+ *                 block's k_rho band (narrowest profiles; one carrier per
+ *                 pixel and channel for the whole block).  PL_REF_MIN_K: the
+ *                 paper's k_rho0 = k_rho at the lowest wavenumber k_0 of the
+ *                 sweep, per k_z bin (Sec. II-A after eq. 8, Sec. II-B after
+ *                 eq. 19); where k_0 is evanescent, the smallest real k_rho
+ *                 of the bin.  Its profiles span [0, max k_rho - k_rho0], so
+ *                 the range grid is about twice as fine at the same
+ *                 l_oversample, and the carrier is formed per (k_z, pixel,
+ *                 channel): it runs the NUFFT range compression (any
+ *                 precision) and the k_z-per-lane back-projection with one
+ *                 bin per lane and 4 wavefronts (PL_EUNSUPPORTED for other
+ *                 range methods, the matrix-core back-projection, kz_block,
+ *                 kz_per_lane > 1 or 8 wavefronts).
  */
 typedef struct pl_hybrid_opts {
     int32_t precision;
@@ -275,6 +298,7 @@ typedef struct pl_hybrid_opts {
     int32_t tile_y;
     int32_t kz_block;
     int32_t range_method;
+    int32_t ref_mode;
 } pl_hybrid_opts;
 
 /* Sizes the plan derives for (geometry, grid, options); see hybrid_plan_info. */
@@ -489,11 +513,14 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* batch, const float* const* e
  * not written in the paper; the matched filter of eqs. 1/10 with weight k_f):
  *   g(x,y,z_m) = sum_c sum_m' sum_f k_f s[c,m',f] exp(+j k_f (R_T + R_R)),
  * over all channels and scan positions, for image planes z_m with
- * m in [iz0, iz0 + nz).  image_dev is [nz][ny][nx] complex64.
- * ws: at least bp_workspace_bytes (the k_f-weighted echo).
- * Errors: PL_EINVAL, PL_EWORKSPACE, PL_EDEVICE.
+ * m in [iz0, iz0 + nz).  image_dev is [nz][ny][nx] complex64.  The
+ * frequencies must be uniform (the sweep of make_geometry) and at most 4096.
+ * ws: 256-byte aligned, at least bp_workspace_bytes(geom, grid, nz) (the
+ * k_f-weighted echo and, for thin slabs whose (channel, scan) rows are split
+ * over several workgroups, their partial images, summed in a fixed order).
+ * Errors: PL_EINVAL, PL_EWORKSPACE, PL_EUNSUPPORTED, PL_EDEVICE.
  */
-int bp_workspace_bytes(const pl_geometry* geom, size_t* bytes);
+int bp_workspace_bytes(const pl_geometry* geom, const pl_image_grid* grid, int32_t nz, size_t* bytes);
 int reconstruct_bp(const pl_geometry* geom, const pl_image_grid* grid, int32_t iz0, int32_t nz,
                    const float* echo_dev, float* image_dev, void* ws, size_t ws_bytes,
                    hipStream_t stream);

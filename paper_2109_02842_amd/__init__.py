@@ -27,6 +27,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 INTERPS = {"bspline4": 0, "lagrange4": 1, "linear": 2}
 BP_KERNELS = {0: "kz-lanes", 1: "pixel-lanes", 2: "mfma", 3: "mfma-1pass"}
 RANGE_METHODS = {"nufft": 0, "resample": 1}
+REF_MODES = {"band-centre": 0, "min-k": 1}
 WARN_ELEMENT_SPACING, WARN_SCAN_STEP = 1, 2
 
 _ERRNAMES = {PL_EINVAL: "PL_EINVAL", PL_EGEOM: "PL_EGEOM", PL_EDEVICE: "PL_EDEVICE",
@@ -61,7 +62,7 @@ class HybridOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("interp", C.c_int32), ("l_oversample", C.c_double),
                 ("nufft_tol", C.c_double), ("tile", C.c_int32), ("kz_per_lane", C.c_int32),
                 ("waves", C.c_int32), ("mfma_backprojection", C.c_int32), ("tile_y", C.c_int32),
-                ("kz_block", C.c_int32), ("range_method", C.c_int32)]
+                ("kz_block", C.c_int32), ("range_method", C.c_int32), ("ref_mode", C.c_int32)]
 
 
 class HybridPlanInfo(C.Structure):
@@ -102,7 +103,7 @@ _SIGNATURES = {
     "backproject": (C.c_int, [_P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), _P, _P, _P,
                               C.c_size_t, _P]),
     "kz_ifft": (C.c_int, [_P, C.POINTER(ImageGridC), _P, _P, _P, C.c_size_t, _P]),
-    "bp_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "bp_workspace_bytes": (C.c_int, [_P, C.POINTER(ImageGridC), C.c_int32, C.POINTER(C.c_size_t)]),
     "reconstruct_bp": (C.c_int, [_P, C.POINTER(ImageGridC), C.c_int32, C.c_int32, _P, _P, _P,
                                  C.c_size_t, _P]),
     "make_hybrid_batch": (C.c_int, [C.c_int32, _P, C.POINTER(ImageGridC), C.POINTER(HybridOpts), C.POINTER(_P)]),
@@ -223,16 +224,19 @@ def _grid(grid) -> ImageGridC:
 
 
 def _opts(precision="fp32", interp="bspline4", l_oversample=6.0, nufft_tol=1e-6, tile=0, kz_per_lane=0,
-          waves=0, mfma_backprojection=0, tile_y=0, kz_block=0, range_method="nufft") -> HybridOpts:
+          waves=0, mfma_backprojection=0, tile_y=0, kz_block=0, range_method="nufft",
+          ref_mode="band-centre") -> HybridOpts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {list(PRECISIONS)}")
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {list(INTERPS)}")
     if range_method not in RANGE_METHODS:
         raise ValueError(f"range_method must be one of {list(RANGE_METHODS)}")
+    if ref_mode not in REF_MODES:
+        raise ValueError(f"ref_mode must be one of {list(REF_MODES)}")
     return HybridOpts(PRECISIONS[precision], INTERPS[interp], float(l_oversample), float(nufft_tol),
                       int(tile), int(kz_per_lane), int(waves), int(mfma_backprojection), int(tile_y),
-                      int(kz_block), RANGE_METHODS[range_method])
+                      int(kz_block), RANGE_METHODS[range_method], REF_MODES[ref_mode])
 
 
 def check_sampling(geom: Geometry, grid) -> int:
@@ -596,9 +600,10 @@ def kz_ifft(geom: Geometry, grid, spectrum, out=None, ws=None):
     return out
 
 
-def bp_workspace_bytes(geom: Geometry) -> int:
+def bp_workspace_bytes(geom: Geometry, grid, nz: Optional[int] = None) -> int:
     n = C.c_size_t()
-    _check(lib().bp_workspace_bytes(geom.handle, C.byref(n)))
+    nz = geom.n_scan if nz is None else nz
+    _check(lib().bp_workspace_bytes(geom.handle, C.byref(_grid(grid)), int(nz), C.byref(n)))
     return int(n.value)
 
 
@@ -606,7 +611,7 @@ def reconstruct_bp(geom: Geometry, grid, echo, iz0: int = 0, nz: Optional[int] =
     """Brute-force back-projection image [nz][ny][nx] for scan planes [iz0, iz0+nz)."""
     torch = _torch()
     nz = geom.n_scan - iz0 if nz is None else nz
-    ws = _ws(ws, bp_workspace_bytes(geom))
+    ws = _ws(ws, bp_workspace_bytes(geom, grid, nz))
     shape = (nz, grid.ny, grid.nx)
     if out is None:
         out = torch.empty(shape, dtype=torch.complex64, device=echo.device)

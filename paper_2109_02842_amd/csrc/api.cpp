@@ -283,10 +283,12 @@ int adjoint_hybrid(const pl_geometry* g, const pl_image_grid* grid, const pl_hyb
     return launch_scan_fft_adjoint(g, St, reinterpret_cast<float2*>(echo), p.zfft, ztab, stream);
 }
 
-int bp_workspace_bytes(const pl_geometry* g, size_t* bytes) {
+int bp_workspace_bytes(const pl_geometry* g, const pl_image_grid* grid, int32_t nz, size_t* bytes) {
     pl::clear_error();
-    if (!g || !bytes) return pl::fail(PL_EINVAL, "bp_workspace_bytes: null pointer");
-    *bytes = static_cast<size_t>(g->n_ch) * g->n_scan * g->n_freq * 8;
+    if (!g || !grid || !bytes) return pl::fail(PL_EINVAL, "bp_workspace_bytes: null pointer");
+    if (grid->nx < 1 || grid->ny < 1 || nz < 1 || nz > g->n_scan)
+        return pl::fail(PL_EINVAL, "bp_workspace_bytes: bad grid or plane count");
+    *bytes = pl::bp_layout(g, grid, nz).bytes;
     return PL_OK;
 }
 
@@ -299,12 +301,14 @@ int reconstruct_bp(const pl_geometry* g, const pl_image_grid* grid, int32_t iz0,
         return fail(PL_EINVAL, "reconstruct_bp: bad grid");
     if (iz0 < 0 || nz < 1 || iz0 + nz > g->n_scan)
         return fail(PL_EINVAL, "reconstruct_bp: planes [%d, %d) outside [0, %d)", iz0, iz0 + nz, g->n_scan);
-    const size_t need = static_cast<size_t>(g->n_ch) * g->n_scan * g->n_freq * 8;
+    const size_t need = bp_layout(g, grid, nz).bytes;
     if (!ws || ws_bytes < need) return fail(PL_EWORKSPACE, "reconstruct_bp: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+        return fail(PL_EWORKSPACE, "reconstruct_bp: workspace must be 256-byte aligned");
     DeviceTables dt;
     int rc = g->device_tables(&dt, stream);
     if (rc) return rc;
-    return launch_bp(g, dt, grid, iz0, nz, reinterpret_cast<const float2*>(echo), static_cast<float2*>(ws),
+    return launch_bp(g, dt, grid, iz0, nz, reinterpret_cast<const float2*>(echo), static_cast<char*>(ws),
                      reinterpret_cast<float2*>(image), stream);
 }
 

@@ -109,6 +109,7 @@ struct HybridPlan {
     bool bp_mfma_sp = false;         // its single-pass form (scaled FP16 q, one product per pair)
     bool bp_gather = false;          // VALU back-projection with one pixel per lane
     int range_method = PL_RANGE_NUFFT;
+    int ref_mode = PL_REF_BAND_CENTRE;  // reference wavenumber: per k_z block, or the paper's per k_z
     double dkl = 0, k0 = 0, dk = 0;  // resampling: uniform k_L step, frequency grid start and step
     double half_band = 0, sigma_used = 0;
     // range grid and NUFFT
@@ -127,12 +128,29 @@ struct HybridPlan {
     float coef[4][4] = {};
     // workspace layout (byte offsets, 256-aligned)
     size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_zfft = 0, off_tw_fine = 0;
-    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0, off_qexp = 0,
-           total = 0;
+    size_t off_deap = 0, off_kp = 0, off_wk = 0, off_krz = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0,
+           off_qexp = 0, total = 0;
 };
 
+// Per (pixel tile, channel) geometry, computed once per call in float64
+// (tile-major: entry tile * n_ch + c).  A pixel's range follows from the
+// tile centre's in float32 without loss: with X the vector from an antenna
+// to the centre, D = |X| and d the pixel's offset from the centre,
+// |X + d| - D = s / (D + sqrt(D^2 + s)), s = 2 X.d + d.d, a difference of at
+// most a tile diagonal, exact to float32 rounding.
+struct GatherTileEntry {
+    double lc;             // range rho_T + rho_R from the channel to the tile centre
+    int win;               // first staged sample of the tile's window (even)
+    int base;              // floor(u(centre)) - 1 - win
+    float uf;              // u(centre) - floor(u(centre)), u = (l - l_lo) / du
+    float xt, yt, dt;      // centre minus Tx position, and its length
+    float xr, yr, dr;      // centre minus Rx position, and its length
+    float pad_;
+};
+static_assert(sizeof(GatherTileEntry) == 48, "tile table entry");
+
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
-size_t backproject_mfma_lds_bytes(int n_ch, int kz_block, bool single_pass);
+size_t backproject_mfma_lds_bytes(int kz_block, bool single_pass);
 size_t backproject_gather_lds_bytes(int rows, int row_chunks);
 
 // Batched pixel-per-lane back-projection (one persistent launch for several
@@ -159,10 +177,11 @@ int reconstruct_impl(const pl_geometry* g, const pl_image_grid* grid, const pl_h
 
 // ---------------------------------------------------------- launchers
 int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
-// Per (tile, channel) geometry of the pixel-per-lane back-projection (after
-// the plan tables: reads l_lo); a no-op for plans without that kernel.
-size_t gather_table_bytes(const HybridPlan& p);
-int launch_gather_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
+// Per (tile, channel) geometry of the pixel-per-lane and matrix-core
+// back-projections (after the plan tables: reads l_lo); a no-op for plans
+// without those kernels.
+size_t tile_table_bytes(const HybridPlan& p);
+int launch_tile_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s);
 // The transforms take the tables of f at `tables`.
 int launch_scan_fft(const pl_geometry* g, const float2* echo, float2* spec, const AxisFft& f, const char* tables,
                     hipStream_t s);
@@ -188,7 +207,16 @@ int launch_scan_fft_adjoint(const pl_geometry* g, const float2* St, float2* echo
                             const char* tables, hipStream_t s);
 int launch_simulate(const pl_geometry* g, const DeviceTables& dt, int n_scat, const double* xyz,
                     const double* refl, float2* echo, hipStream_t s);
+// Brute-force BP over image planes [iz0, iz0 + nz): workspace layout (the
+// k_f-weighted echo, then, when the (channel, scan) rows are split over
+// n_seg workgroup segments, their partial images [n_seg][nz][ny][nx]).
+struct BpLayout {
+    int ch = 1, n_seg = 1;          // rows staged per LDS buffer; row segments
+    long long rows_per_seg = 0;
+    size_t off_part = 0, bytes = 0;
+};
+BpLayout bp_layout(const pl_geometry* g, const pl_image_grid* grid, int nz);
 int launch_bp(const pl_geometry* g, const DeviceTables& dt, const pl_image_grid* grid, int iz0,
-              int nz, const float2* echo, float2* weighted, float2* image, hipStream_t s);
+              int nz, const float2* echo, char* ws, float2* image, hipStream_t s);
 
 }  // namespace pl

@@ -56,10 +56,14 @@ __device__ __forceinline__ float rdl(float v, int lane) {
 // TX x TY pixel tile, KPL k_z bins per lane (a block of 64 * KPL bins shares
 // one reference wavenumber), NW wavefronts per block, OCC the wavefronts per
 // SIMD the LDS footprint allows (it caps the registers at 512 / OCC).
-template <int TX, int TY, int KPL, int NW, int OCC>
+// KZREF: every k_z bin has its own reference krz[kz] (the paper's k_rho0 of
+// eq. 8b/19b), so each lane forms its carrier per (pixel, channel) from the
+// broadcast float64 range, range-reduced in float64.
+template <int TX, int TY, int KPL, int NW, int OCC, bool KZREF>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) void backproject_kernel(const float2* __restrict__ q,
                                                               const double* __restrict__ chan,
-                                                              const double* __restrict__ llo, BpjArgs a,
+                                                              const double* __restrict__ llo,
+                                                              const double* __restrict__ krz, BpjArgs a,
                                                               float2* __restrict__ G) {
     constexpr int NT = 64 * NW;
     constexpr int PPW = TX * TY / NW;   // pixels per wavefront
@@ -81,6 +85,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform
     const double kref_rev = a.kref[blk] * (0.5 / kPi);
+    double krz_rev[KPL];
+#pragma unroll
+    for (int r = 0; r < KPL; ++r)
+        krz_rev[r] = KZREF ? krz[min(blk * ROWS + (tid & 63) + 64 * r, a.n_z - 1)] * (0.5 / kPi) : 0.0;
     const int buf_stride = ROWS * a.wpad;
 
     // window start of every channel for this tile
@@ -159,6 +167,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
         // taps and cubic weights, carrier exp(j k_ref l) with float64 phase
         int my_i0 = 0;
         float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, cr = 0.f, ci = 0.f;
+        double my_l = 0.0;
         {
             const int c = c0 + lane / PPW;
             if (c < a.n_ch && pvalid) {
@@ -174,9 +183,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
                 w1 = ((a.coef[1][3] * t + a.coef[1][2]) * t + a.coef[1][1]) * t + a.coef[1][0];
                 w2 = ((a.coef[2][3] * t + a.coef[2][2]) * t + a.coef[2][1]) * t + a.coef[2][0];
                 w3 = ((a.coef[3][3] * t + a.coef[3][2]) * t + a.coef[3][1]) * t + a.coef[3][0];
-                const float2 car = cis_rev(kref_rev * l);
-                cr = car.x;
-                ci = car.y;
+                if (KZREF) {
+                    my_l = l;
+                } else {
+                    const float2 car = cis_rev(kref_rev * l);
+                    cr = car.x;
+                    ci = car.y;
+                }
             }
         }
 #pragma unroll 1
@@ -190,10 +203,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
                 const int L = cc * PPW + j;
                 const int i0 = __builtin_amdgcn_readlane(my_i0, L);
                 const float v0 = rdl(w0, L), v1 = rdl(w1, L), v2 = rdl(w2, L), v3 = rdl(w3, L);
-                const float kr = rdl(cr, L), ki = rdl(ci, L);
+                float kr = rdl(cr, L), ki = rdl(ci, L);
+                double lb = 0.0;
+                if (KZREF) {
+                    const long long bits = __double_as_longlong(my_l);
+                    const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits), L);
+                    const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), L);
+                    lb = __hiloint2double(hi, lo);
+                }
                 const float2* b = base + i0;
 #pragma unroll
                 for (int r = 0; r < KPL; ++r) {
+                    if (KZREF) {
+                        const float2 car = cis_rev(krz_rev[r] * lb);
+                        kr = car.x;
+                        ki = car.y;
+                    }
                     const float2* br = b + r * 64 * a.wpad;
                     const float2 q0 = br[0], q1 = br[1], q2 = br[2], q3 = br[3];
                     const float re = v0 * q0.x + v1 * q1.x + v2 * q2.x + v3 * q3.x;
@@ -223,17 +248,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC))) 
     }
 }
 
-template <int TX, int TY, int KPL, int NW, int OCC>
+template <int TX, int TY, int KPL, int NW, int OCC, bool KZREF = false>
 int launch_variant(const BpjArgs& a, size_t smem, unsigned blocks, hipStream_t s, const float2* q,
-                   const double* chan, const double* llo, float2* G) {
-    auto fn = backproject_kernel<TX, TY, KPL, NW, OCC>;
+                   const double* chan, const double* llo, const double* krz, float2* G) {
+    auto fn = backproject_kernel<TX, TY, KPL, NW, OCC, KZREF>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(smem));
         if (e != hipSuccess) return fail(PL_EDEVICE, "back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, q, chan, llo, a, G);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, q, chan, llo, krz, a, G);
     return check_launch("back-projection");
 }
 
@@ -261,22 +286,8 @@ struct BpgArgs {
     double kref[kMaxBlocks];
 };
 
-// Per (8x8 tile, channel) geometry of the pixel-per-lane back-projection,
-// computed once per call in float64 (tile-major: entry tile * n_ch + c).  A
-// pixel's range follows from the tile centre's in float32 without loss:
-// with X the vector from an antenna to the centre, D = |X| and d the
-// pixel's offset, |X + d| - D = s / (D + sqrt(D^2 + s)), s = 2 X.d + d.d,
-// a difference of at most a tile diagonal, exact to float32 rounding.
-struct GatherTileEntry {
-    double lc;             // range rho_T + rho_R from the channel to the tile centre
-    int win;               // first staged sample of the tile's window (even)
-    int base;              // floor(u(centre)) - 1 - win
-    float uf;              // u(centre) - floor(u(centre)), u = (l - l_lo) / du
-    float xt, yt, dt;      // centre minus Tx position, and its length
-    float xr, yr, dr;      // centre minus Rx position, and its length
-    float pad_;
-};
-static_assert(sizeof(GatherTileEntry) == 48, "tile table entry");
+// GatherTileEntry (internal.hpp): the per (tile, channel) geometry table.
+
 
 // One scan of a batch: its arguments and byte offsets of its range profiles,
 // tile table and spectrum in the batch workspace.
@@ -468,22 +479,30 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(c
     gather_tile<KB, RSC>(a, q, tab, G, blk, work - blk * a.n_tiles, smem);
 }
 
-// The tile table (see GatherTileEntry), one thread per (tile, channel).
-__global__ void gather_table_kernel(BpgArgs a, const double* __restrict__ chan, const double* __restrict__ llo,
-                                    GatherTileEntry* __restrict__ tab) {
+struct TileTableArgs {
+    int n_ch, n_l, tiles_x, n_tiles, tile_x, tile_y, wpl;
+    int pad_;
+    double x0, y0, dx, dy, inv_du, reach;
+};
+
+// The tile table (see GatherTileEntry), one thread per (tile, channel): the
+// tile's centre, its range from the channel's antennas in float64, the
+// even start of the channel's staged window (wpl samples) and the centre's
+// first tap and fractional position relative to it.
+__global__ void tile_table_kernel(TileTableArgs a, const double* __restrict__ chan, const double* __restrict__ llo,
+                                  GatherTileEntry* __restrict__ tab) {
     const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
-    const int wpl = 2 * a.nchk;
     for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < n;
          e += static_cast<long long>(gridDim.x) * blockDim.x) {
         const int tile = static_cast<int>(e / a.n_ch), c = static_cast<int>(e - static_cast<long long>(tile) * a.n_ch);
-        const int tx0 = (tile % a.tiles_x) * 8, ty0 = (tile / a.tiles_x) * 8;
-        const double cx = a.x0 + (tx0 + 3.5) * a.dx, cy = a.y0 + (ty0 + 3.5) * a.dy;
+        const int tx0 = (tile % a.tiles_x) * a.tile_x, ty0 = (tile / a.tiles_x) * a.tile_y;
+        const double cx = a.x0 + (tx0 + 0.5 * (a.tile_x - 1)) * a.dx, cy = a.y0 + (ty0 + 0.5 * (a.tile_y - 1)) * a.dy;
         const double* ch = chan + 4 * c;
         const double xt = cx - ch[0], yt = cy - ch[1], xr = cx - ch[2], yr = cy - ch[3];
         const double dt = sqrt(xt * xt + yt * yt), dr = sqrt(xr * xr + yr * yr);
         const double l = dt + dr;
         int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
-        s = max(0, min(s, a.n_l - wpl)) & ~1;
+        s = max(0, min(s, a.n_l - a.wpl)) & ~1;
         const double u = (l - llo[c]) * a.inv_du;
         const double fl = floor(u);
         GatherTileEntry t;
@@ -939,16 +958,30 @@ size_t backproject_gather_lds_bytes(int rows, int row_chunks) {
     return 1ull * kGatherBatch * 2 * 64 * 16 + 2ull * rows * row_chunks * 16;
 }
 
-size_t gather_table_bytes(const HybridPlan& p) {
-    return static_cast<size_t>(p.tiles_x) * p.tiles_y * p.n_ch * sizeof(GatherTileEntry);
+size_t tile_table_bytes(const HybridPlan& p) {
+    return (p.bp_gather || p.bp_mfma) ? static_cast<size_t>(p.tiles_x) * p.tiles_y * p.n_ch * sizeof(GatherTileEntry)
+                                      : 0;
 }
 
-int launch_gather_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s) {
-    if (!p.bp_gather) return PL_OK;
-    const BpgArgs a = gather_args(p);
+int launch_tile_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s) {
+    if (!p.bp_gather && !p.bp_mfma) return PL_OK;
+    TileTableArgs a{};
+    a.n_ch = p.n_ch;
+    a.n_l = p.n_l;
+    a.tiles_x = p.tiles_x;
+    a.n_tiles = p.tiles_x * p.tiles_y;
+    a.tile_x = p.tile_x;
+    a.tile_y = p.tile_y;
+    a.wpl = p.bp_gather ? p.window : 8 * (p.window / 8);  // staged samples per row (plane)
+    a.x0 = p.x0;
+    a.y0 = p.y0;
+    a.dx = p.dx;
+    a.dy = p.dy;
+    a.inv_du = 1.0 / p.du;
+    a.reach = std::hypot((p.tile_x - 1) * p.dx, (p.tile_y - 1) * p.dy);  // 2 x the tile's half-diagonal
     const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
     const int blocks = static_cast<int>(std::min<long long>((n + 255) / 256, 8192));
-    hipLaunchKernelGGL(gather_table_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan,
+    hipLaunchKernelGGL(tile_table_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan,
                        reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<GatherTileEntry*>(ws + p.off_tiles));
     return check_launch("back-projection tile table");
 }
@@ -991,10 +1024,19 @@ int launch_backproject(const HybridPlan& p, const DeviceTables& dt, const float2
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
+    const double* krz = reinterpret_cast<const double*>(ws + p.off_krz);
     const int kpl = p.block / kLanes;
+    if (p.ref_mode == PL_REF_MIN_K) {
+        if (kpl != 1 || p.waves != 4)
+            return fail(PL_EUNSUPPORTED, "per-k_z references run one k_z bin per lane, 4 wavefronts");
+        if (p.tile_x == 8 && p.tile_y == 8) return launch_variant<8, 8, 1, 4, 4, true>(a, smem, blocks, s, q, dt.chan, llo, krz, G);
+        if (p.tile_x == 4 && p.tile_y == 4) return launch_variant<4, 4, 1, 4, 4, true>(a, smem, blocks, s, q, dt.chan, llo, krz, G);
+        if (p.tile_x == 2 && p.tile_y == 2) return launch_variant<2, 2, 1, 4, 4, true>(a, smem, blocks, s, q, dt.chan, llo, krz, G);
+        return fail(PL_EUNSUPPORTED, "no per-k_z-reference back-projection for tile %dx%d", p.tile_x, p.tile_y);
+    }
 #define PL_CASE(TX, TY, K, NW, OCC)                                                   \
     if (p.tile_x == TX && p.tile_y == TY && kpl == K && p.waves == NW)                \
-        return launch_variant<TX, TY, K, NW, OCC>(a, smem, blocks, s, q, dt.chan, llo, G);
+        return launch_variant<TX, TY, K, NW, OCC>(a, smem, blocks, s, q, dt.chan, llo, krz, G);
     PL_CASE(8, 8, 1, 4, 4) PL_CASE(8, 8, 2, 4, 2) PL_CASE(8, 8, 4, 4, 1)
     PL_CASE(8, 8, 1, 8, 4) PL_CASE(8, 8, 2, 8, 4) PL_CASE(8, 8, 4, 8, 2)
     PL_CASE(4, 4, 1, 4, 4) PL_CASE(4, 4, 2, 4, 2) PL_CASE(4, 4, 4, 4, 1)

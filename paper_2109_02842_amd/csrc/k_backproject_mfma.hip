@@ -57,12 +57,16 @@ constexpr int kRowChunks = 33;              // 16-byte chunks per LDS row (split
 constexpr int kRowChunksSP = 17;            // single-pass form
 constexpr int kPlaneBytes = 128;            // 8 chunks per plane
 __host__ __device__ constexpr int row_chunks(bool sp) { return sp ? kRowChunksSP : kRowChunks; }
+// channels staged per barrier: two in the single-pass form with 64 k_z bins
+// (its rows are half as long, so two channels' double buffers still fit two
+// workgroups per CU), else one
+__host__ __device__ constexpr int stage_channels(bool sp, int kz_block) { return sp && kz_block == 64 ? 2 : 1; }
 constexpr int kSelEntries = 20;             // selector table: a0 = 4h - d0 in [-15, 4]
 
 struct BpmArgs {
-    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, win_bytes;
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, mono;
     const int* qexp;  // single-pass form: the profiles' scale exponent g
-    double x0, y0, dx, dy, inv_du, reach;
+    double x0, y0, dx, dy, inv_du;
     float coef[4][4];  // tap j weight = sum_k coef[j][k] t^k, taps at floor(u) - 1 + j
     double kref[kMaxBlocks];
 };
@@ -87,15 +91,6 @@ __host__ __device__ constexpr unsigned tap_sel(int k) {
     return (k >= 0 && k < 4) ? 0x0100u + 0x0202u * static_cast<unsigned>(k) : 0x0c0cu;
 }
 
-// sqrt(x) for x >= 0 to double precision: hardware FP32 root (about 1 ulp),
-// then one Newton step whose residual is formed in FP64.
-__device__ __forceinline__ double sqrt_dp(double x) {
-    const float r = __builtin_amdgcn_sqrtf(static_cast<float>(x));
-    const double rd = r;
-    const float corr = static_cast<float>(x - rd * rd) * (0.5f * __builtin_amdgcn_rcpf(r));
-    return r > 0.f ? rd + static_cast<double>(corr) : 0.0;
-}
-
 // 16-byte direct global-to-LDS copy.  The 16-byte form of the builtin exists
 // for the device target only; the host pass of this translation unit, which
 // emits the launch stubs, must not see it.
@@ -104,6 +99,17 @@ __device__ __forceinline__ double sqrt_dp(double x) {
 #else
 #define PL_DMA16(SRC, DST) ((void)(SRC), (void)(DST))
 #endif
+
+// Window start of a tile-table entry through the constant address space: a
+// scalar load (lgkmcnt), so that taking it never waits for the row copies in
+// flight (vmcnt), as a vector load would.  The address is wavefront-uniform.
+__device__ __forceinline__ int entry_win(const GatherTileEntry* e) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *reinterpret_cast<const __attribute__((address_space(4))) int*>(reinterpret_cast<unsigned long long>(&e->win));
+#else
+    return e->win;
+#endif
+}
 
 // This wavefront's share of one channel's window rows: instruction
 // i = wave + NW j fills LDS chunks [64 i, 64 i + 64) of the buffer at DST0;
@@ -123,10 +129,8 @@ __device__ __forceinline__ double sqrt_dp(double x) {
 // workgroups per CU), which caps a wavefront at 128 registers.
 template <int GPW, int KT, int NW, bool SP>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 1)))
-void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
-                                                               const double* __restrict__ chan,
-                                                               const double* __restrict__ llo, BpmArgs a,
-                                                               float2* __restrict__ G) {
+void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const GatherTileEntry* __restrict__ tab,
+                             BpmArgs a, float2* __restrict__ G) {
     constexpr int KB = 16 * KT;
     constexpr int NG = GPW * NW;                                    // groups per tile
     constexpr int GX = NG == 4 ? 2 : 4, GY = NG / GX;
@@ -135,10 +139,10 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     constexpr int RC = row_chunks(SP), RB = 16 * RC, NP = SP ? 2 : 4;  // row chunks, row bytes, planes
     constexpr int NIW = (KB * RC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
     constexpr unsigned kBufBytes = KB * RB;
+    constexpr int CPS = stage_channels(SP, KB);
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    int* win = reinterpret_cast<int*>(smem);
-    u32x4* sel_tab = reinterpret_cast<u32x4*>(smem + a.win_bytes);
-    const unsigned lds0 = static_cast<unsigned>(a.win_bytes + kSelEntries * 16);
+    u32x4* sel_tab = reinterpret_cast<u32x4*>(smem);
+    constexpr unsigned lds0 = kSelEntries * 16;
 
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
     if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
@@ -149,19 +153,10 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpl = 8 * a.nck;  // staged samples per plane
     const double kref_rev = a.kref[blk] * (0.5 / kPi);
+    const float kref_rev_f = static_cast<float>(kref_rev);
+    const float inv_du_f = static_cast<float>(a.inv_du);
+    const GatherTileEntry* tt = tab + static_cast<size_t>(tile) * a.n_ch;
 
-    // even window start of every channel for this tile
-    {
-        const double cx = a.x0 + (tx0 + 0.5 * (TX - 1)) * a.dx, cy = a.y0 + (ty0 + 0.5 * (TY - 1)) * a.dy;
-        for (int c = tid; c < a.n_ch; c += 64 * NW) {
-            const double* ch = chan + 4 * c;
-            const double l = sqrt((cx - ch[0]) * (cx - ch[0]) + (cy - ch[1]) * (cy - ch[1])) +
-                             sqrt((cx - ch[2]) * (cx - ch[2]) + (cy - ch[3]) * (cy - ch[3]));
-            int s = static_cast<int>(floor((l - a.reach - llo[c]) * a.inv_du)) - 2;
-            s = max(0, min(s, a.n_l - wpl));
-            win[c] = s & ~1;
-        }
-    }
     // selectors of the sample pairs (a, a+1), (a+2, a+3), (a+8, a+9),
     // (a+10, a+11) in tap units, a = a0 = 4h - d0, entry a0 + 15
     if (tid < kSelEntries) {
@@ -190,14 +185,19 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
     }
     const size_t chan_elems = static_cast<size_t>(a.n_z) * NP * a.n_l;
 
-    // pixel of this lane within a group, k' group of the MFMA operands
+    // pixel pn of each group (the operand column of this lane), its offset
+    // from the tile centre; k' group of the MFMA operands
     const int pn = lane & 15, kg = lane >> 4, h = kg & 1;
     int gpx[GPW], gpy[GPW];
+    float ox[GPW], oy[GPW];
 #pragma unroll
     for (int g = 0; g < GPW; ++g) {
         const int gi = wave * GPW + g;
-        gpx[g] = tx0 + 4 * (gi % GX) + (pn & 3);
-        gpy[g] = ty0 + 4 * (gi / GX) + (pn >> 2);
+        const int lx = 4 * (gi % GX) + (pn & 3), ly = 4 * (gi / GX) + (pn >> 2);
+        gpx[g] = tx0 + lx;
+        gpy[g] = ty0 + ly;
+        ox[g] = (lx - 0.5f * (TX - 1)) * static_cast<float>(a.dx);
+        oy[g] = (ly - 0.5f * (TY - 1)) * static_cast<float>(a.dy);
     }
 
     f32x4 accr[GPW][KT], acci[GPW][KT];
@@ -209,10 +209,14 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
             acci[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
 
-    __syncthreads();  // window starts and selector table visible
-    PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + __builtin_amdgcn_readfirstlane(win[0])), smem + lds0);
+    // channel c's rows go to buffer (c / CPS) % 2 * CPS + c % CPS
+#pragma unroll
+    for (int k = 0; k < CPS; ++k)
+        if (k < a.n_ch)
+            PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + k * chan_elems + entry_win(tt + k)),
+                          smem + lds0 + k * kBufBytes);
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    __syncthreads();  // selector table and the first channels' rows visible
 
     // LDS byte offset of this lane's A operand within a buffer: row m = lane
     // & 15 of a k_z tile, hi plane (split: 0 real, 2 imaginary; SP: 0, 1),
@@ -228,43 +232,60 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
-        // weights of (pixel pn of group g, channel c0 + lane / 16)
+        // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
+        // each group and channel c0 + k: its range from the tile table
+        // (float64 centre, float32 offset), its position in the group's
+        // 16-sample window and its carrier; the MFMA lanes (pn, kg) of
+        // channel c0 + cc read them from lane 16 cc + pn.
         float xw[GPW], crw[GPW], ciw[GPW];
         int srw[GPW];
         {
             const int c = min(c0 + (lane >> 4), a.n_ch - 1);
-            const double* ch = chan + 4 * c;
-            const double xT = ch[0], yT = ch[1], xR = ch[2], yR = ch[3], lo = llo[c];
-            const int cw = win[c];
+            const GatherTileEntry e = tt[c];
+            const float2 cc0 = cis_rev(kref_rev * e.lc);   // the centre's carrier, float64 phase
 #pragma unroll
             for (int g = 0; g < GPW; ++g) {
                 const bool ok = gpx[g] < a.nx && gpy[g] < a.ny;
-                const double xg = a.x0 + gpx[g] * a.dx, yg = a.y0 + gpy[g] * a.dy;
-                const double lpath = sqrt_dp((xg - xT) * (xg - xT) + (yg - yT) * (yg - yT)) +
-                                     sqrt_dp((xg - xR) * (xg - xR) + (yg - yR) * (yg - yR));
-                const double u = (lpath - lo) * a.inv_du;
-                int m = ok ? static_cast<int>(floor(u)) - 1 : 0x3fffffff;
+                const float oo = ox[g] * ox[g] + oy[g] * oy[g];
+                const float sT = 2.f * (e.xt * ox[g] + e.yt * oy[g]) + oo;
+                float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
+                if (a.mono) {
+                    dl += dl;
+                } else {
+                    const float sR = 2.f * (e.xr * ox[g] + e.yr * oy[g]) + oo;
+                    dl += sR * __builtin_amdgcn_rcpf(e.dr + __builtin_amdgcn_sqrtf(e.dr * e.dr + sR));
+                }
+                const float uu = e.uf + dl * inv_du_f;
+                const float fv = floorf(uu);
+                const int i0 = e.base + static_cast<int>(fv);   // first tap, from the window start
+                int m = ok ? i0 : 0x3fffffff;
                 m = min(m, __shfl_xor(m, 1));
                 m = min(m, __shfl_xor(m, 2));
                 m = min(m, __shfl_xor(m, 4));
                 m = min(m, __shfl_xor(m, 8));
-                const int sr = m == 0x3fffffff ? 0 : max(0, min((m - cw) & ~3, wpl - 16));
+                const int sr = m == 0x3fffffff ? 0 : max(0, min(m & ~3, wpl - 16));
                 srw[g] = sr;
-                xw[g] = ok ? static_cast<float>(u - static_cast<double>(cw + sr)) : 1000.f;
-                const float2 car = ok ? cis_rev(kref_rev * lpath) : make_float2(0.f, 0.f);
-                crw[g] = car.x;
-                ciw[g] = car.y;
+                // position in the group window: floor(x) - 1 is the first tap
+                xw[g] = ok ? static_cast<float>(i0 - sr + 1) + (uu - fv) : 1000.f;
+                const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
+                crw[g] = ok ? cc0.x * c1.x - cc0.y * c1.y : 0.f;
+                ciw[g] = ok ? cc0.x * c1.y + cc0.y * c1.x : 0.f;
             }
         }
 #pragma unroll 1
         for (int cc = 0; cc < 4; ++cc) {
             const int c = c0 + cc;
             if (c >= a.n_ch) break;
-            if (c + 1 < a.n_ch)
-                PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + (c + 1) * chan_elems +
-                                                            __builtin_amdgcn_readfirstlane(win[c + 1])),
-                              smem + lds0 + ((c + 1) & 1) * kBufBytes);
-            const unsigned bufo = lds0 + (c & 1) * kBufBytes;
+            if (c % CPS == 0) {   // the next stage's channels, into the other buffers
+#pragma unroll
+                for (int k = 0; k < CPS; ++k) {
+                    const int cn = c + CPS + k;
+                    if (cn < a.n_ch)
+                        PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + cn * chan_elems + entry_win(tt + cn)),
+                                      smem + lds0 + (((cn / CPS) & 1) * CPS + k) * kBufBytes);
+                }
+            }
+            const unsigned bufo = lds0 + (((c / CPS) & 1) * CPS + c % CPS) * kBufBytes;
             const int src = cc * 16 + pn;
 #pragma unroll
             for (int g = 0; g < GPW; ++g) {
@@ -305,41 +326,43 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
                         accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, br, accr[g][t], 0, 0, 0);
                         acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, bi, acci[g][t], 0, 0, 0);
                     }
-                    continue;
-                }
-                const unsigned rh0 = pack_bf16(r0, r1), rh1 = pack_bf16(r2, r3);
-                const unsigned ih0 = pack_bf16(i0, i1), ih1 = pack_bf16(i2, i3);
-                const unsigned rl0 = pack_lo(r0, r1, rh0), rl1 = pack_lo(r2, r3, rh1);
-                const unsigned il0 = pack_lo(i0, i1, ih0), il1 = pack_lo(i2, i3, ih1);
-                u32x4 vrh, vrl, vih, vil;
+                } else {
+                    const unsigned rh0 = pack_bf16(r0, r1), rh1 = pack_bf16(r2, r3);
+                    const unsigned ih0 = pack_bf16(i0, i1), ih1 = pack_bf16(i2, i3);
+                    const unsigned rl0 = pack_lo(r0, r1, rh0), rl1 = pack_lo(r2, r3, rh1);
+                    const unsigned il0 = pack_lo(i0, i1, ih0), il1 = pack_lo(i2, i3, ih1);
+                    u32x4 vrh, vrl, vih, vil;
 #pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    vrh[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
-                    vrl[o] = __builtin_amdgcn_perm(rl1, rl0, sel[o]);
-                    vih[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
-                    vil[o] = __builtin_amdgcn_perm(il1, il0, sel[o]);
-                }
-                const bf16x8 brh = __builtin_bit_cast(bf16x8, vrh), brl = __builtin_bit_cast(bf16x8, vrl);
-                const bf16x8 bih = __builtin_bit_cast(bf16x8, vih), bil = __builtin_bit_cast(bf16x8, vil);
+                    for (int o = 0; o < 4; ++o) {
+                        vrh[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
+                        vrl[o] = __builtin_amdgcn_perm(rl1, rl0, sel[o]);
+                        vih[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
+                        vil[o] = __builtin_amdgcn_perm(il1, il0, sel[o]);
+                    }
+                    const bf16x8 brh = __builtin_bit_cast(bf16x8, vrh), brl = __builtin_bit_cast(bf16x8, vrl);
+                    const bf16x8 bih = __builtin_bit_cast(bf16x8, vih), bil = __builtin_bit_cast(bf16x8, vil);
 #pragma unroll
-                for (int t = 0; t < KT; ++t) {
-                    const unsigned char* p = ap + t * 16 * RB;
-                    const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
-                    const u32x2 h1 = *reinterpret_cast<const u32x2*>(ap + dq[0] + t * 16 * RB);
-                    const u32x2 l0 = *reinterpret_cast<const u32x2*>(ap + dq[1] + t * 16 * RB);
-                    const u32x2 l1 = *reinterpret_cast<const u32x2*>(ap + dq[2] + t * 16 * RB);
-                    const bf16x8 vah = __builtin_bit_cast(bf16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
-                    const bf16x8 val = __builtin_bit_cast(bf16x8, u32x4{l0[0], l0[1], l1[0], l1[1]});
-                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brh, accr[g][t], 0, 0, 0);
-                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bih, acci[g][t], 0, 0, 0);
-                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brl, accr[g][t], 0, 0, 0);
-                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bil, acci[g][t], 0, 0, 0);
-                    accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, brh, accr[g][t], 0, 0, 0);
-                    acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, bih, acci[g][t], 0, 0, 0);
+                    for (int t = 0; t < KT; ++t) {
+                        const unsigned char* p = ap + t * 16 * RB;
+                        const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
+                        const u32x2 h1 = *reinterpret_cast<const u32x2*>(ap + dq[0] + t * 16 * RB);
+                        const u32x2 l0 = *reinterpret_cast<const u32x2*>(ap + dq[1] + t * 16 * RB);
+                        const u32x2 l1 = *reinterpret_cast<const u32x2*>(ap + dq[2] + t * 16 * RB);
+                        const bf16x8 vah = __builtin_bit_cast(bf16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
+                        const bf16x8 val = __builtin_bit_cast(bf16x8, u32x4{l0[0], l0[1], l1[0], l1[1]});
+                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brh, accr[g][t], 0, 0, 0);
+                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bih, acci[g][t], 0, 0, 0);
+                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, brl, accr[g][t], 0, 0, 0);
+                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vah, bil, acci[g][t], 0, 0, 0);
+                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, brh, accr[g][t], 0, 0, 0);
+                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(val, bih, acci[g][t], 0, 0, 0);
+                    }
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
+            if (c % CPS == CPS - 1 || c + 1 == a.n_ch) {   // end of a stage (workgroup-uniform)
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            }
         }
     }
 
@@ -363,7 +386,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs,
 
 template <int GPW, int KT, int NW, bool SP>
 int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, const unsigned short* qs,
-               const double* chan, const double* llo, float2* G) {
+               const GatherTileEntry* tab, float2* G) {
     auto fn = backproject_mfma_kernel<GPW, KT, NW, SP>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -371,14 +394,14 @@ int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, co
         if (e != hipSuccess)
             return fail(PL_EDEVICE, "MFMA back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, qs, chan, llo, a, G);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, qs, tab, a, G);
     return check_launch("back-projection (MFMA)");
 }
 
 }  // namespace
 
-size_t backproject_mfma_lds_bytes(int n_ch, int kz_block, bool single_pass) {
-    return static_cast<size_t>((n_ch + 3) & ~3) * 4 + kSelEntries * 16 + 2ull * kz_block * 16 * row_chunks(single_pass);
+size_t backproject_mfma_lds_bytes(int kz_block, bool single_pass) {
+    return kSelEntries * 16 + 2ull * stage_channels(single_pass, kz_block) * kz_block * 16 * row_chunks(single_pass);
 }
 
 int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs, char* ws,
@@ -394,29 +417,29 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
     a.n_work = a.n_tiles * p.n_blocks;
     a.per_xcd = (a.n_work + 7) / 8;
     a.nck = p.window / 8;
-    a.win_bytes = ((p.n_ch + 3) & ~3) * 4;
+    a.mono = p.mode == PL_MONO;
     a.qexp = reinterpret_cast<const int*>(ws + p.off_qexp);
     a.x0 = p.x0;
     a.y0 = p.y0;
     a.dx = p.dx;
     a.dy = p.dy;
     a.inv_du = 1.0 / p.du;
-    a.reach = std::hypot((p.tile_x - 1) * p.dx, (p.tile_y - 1) * p.dy);  // 2 x tile half-diagonal
     std::memcpy(a.coef, p.coef, sizeof(a.coef));
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
     if (p.window % 8 || a.nck < 2 || a.nck > 8 || p.window > p.n_l || p.window_pad != row_chunks(p.bp_mfma_sp))
         return fail(PL_EUNSUPPORTED, "MFMA back-projection window %d out of range", p.window);
-    const size_t smem = backproject_mfma_lds_bytes(p.n_ch, p.block, p.bp_mfma_sp);
+    const size_t smem = backproject_mfma_lds_bytes(p.block, p.bp_mfma_sp);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "MFMA back-projection needs %zu bytes of LDS", smem);
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
-    const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
+    const GatherTileEntry* tab = reinterpret_cast<const GatherTileEntry*>(ws + p.off_tiles);
+    (void)dt;
     const int ng = p.tile_x * p.tile_y / 16;
     const int kt = p.block / 16;
     const int nw = p.waves;
 #define PL_BPM(G_, K_, W_)                                                                              \
     if (ng == G_ * W_ && kt == K_ && nw == W_)                                                          \
-        return p.bp_mfma_sp ? launch_cfg<G_, K_, W_, true>(a, smem, blocks, s, qs, dt.chan, llo, G)      \
-                            : launch_cfg<G_, K_, W_, false>(a, smem, blocks, s, qs, dt.chan, llo, G);
+        return p.bp_mfma_sp ? launch_cfg<G_, K_, W_, true>(a, smem, blocks, s, qs, tab, G)               \
+                            : launch_cfg<G_, K_, W_, false>(a, smem, blocks, s, qs, tab, G);
     PL_BPM(1, 4, 4) PL_BPM(1, 8, 4) PL_BPM(2, 4, 4) PL_BPM(2, 8, 4) PL_BPM(4, 4, 4) PL_BPM(4, 8, 4)
     PL_BPM(1, 4, 8) PL_BPM(1, 8, 8) PL_BPM(2, 4, 8)
 #undef PL_BPM

@@ -6,13 +6,29 @@ namespace pl {
 namespace {
 
 struct PlanTablesArgs {
-    int n_ch, n_z, n_f, n_l, n_fine, interp, n_gl, block;
+    int n_ch, n_z, n_f, n_l, n_fine, interp, n_gl, block, ref_mode;
     double du, h, beta, scan_step;
     double gx0, gx1, gy0, gy1;
     double kref[kMaxBlocks];
     double glx[kMaxGL];
     double glw[kMaxGL];
 };
+
+__device__ double kz_of(int kap, int n_z, double step) {
+    const int sk = kap < (n_z + 1) / 2 ? kap : kap - n_z;
+    return 2.0 * kPi * sk / (n_z * step);
+}
+
+// Reference wavenumber of k_z bin kap (see plan_tables_kernel).
+__device__ double kref_of(const PlanTablesArgs& a, const double* __restrict__ k, int kap) {
+    if (a.ref_mode != PL_REF_MIN_K) return a.kref[kap / a.block];
+    const double q = 0.25 * kz_of(kap, a.n_z, a.scan_step) * kz_of(kap, a.n_z, a.scan_step);
+    for (int f = 0; f < a.n_f; ++f) {   // k rises with f: the first real k_rho is the smallest
+        const double arg = k[f] * k[f] - q;
+        if (arg > 0.0) return sqrt(arg);
+    }
+    return 0.0;
+}
 
 __device__ double dist_to_rect(double px, double py, double x0, double x1, double y0, double y1) {
     const double cx = fmin(fmax(px, x0), x1), cy = fmin(fmax(py, y0), y1);
@@ -26,14 +42,18 @@ __device__ double dist_to_rect(double px, double py, double x0, double x1, doubl
 //                rectangle (demodulation reference of the resampling method)
 //   tw_fine[t]   exp(-2 pi i t / n_fine)
 //   deap[i]      1 / (h * FT of the spreading kernel) at output mode i - n_l/2
-//   kp[kz][f]    k' = k_rho - k_ref(block), k_rho = sqrt(k^2 - k_z^2/4) (0 if evanescent)
+//   kp[kz][f]    k' = k_rho - k_ref(kz), k_rho = sqrt(k^2 - k_z^2/4) (0 if evanescent)
 //   wk[kz][f]    k_f (weight of "k dk") times the B-spline prefilter, 0 if evanescent
+//   krz[kz]      the reference k_ref(kz): the block's band centre, or with
+//                PL_REF_MIN_K the paper's k_rho0 = k_rho at the lowest
+//                wavenumber k[0] (the smallest real k_rho of the bin when
+//                k[0] is evanescent there, 0 when nothing propagates)
 __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ chan,
                                    const double* __restrict__ k, double* __restrict__ llo,
                                    double* __restrict__ lref, float2* __restrict__ tw_fine,
                                    float* __restrict__ deap, double* __restrict__ kp,
-                                   float* __restrict__ wk) {
-    const long long n0 = a.n_ch, n1 = n0, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
+                                   float* __restrict__ wk, double* __restrict__ krz) {
+    const long long n0 = a.n_ch, n1 = n0 + a.n_z, n2 = n1 + a.n_fine, n3 = n2 + a.n_l;
     const long long total = n3 + static_cast<long long>(a.n_z) * a.n_f;
     for (long long idx = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; idx < total;
          idx += static_cast<long long>(gridDim.x) * blockDim.x) {
@@ -44,6 +64,9 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
             llo[c] = lmin - 2.0 * a.du;
             const double cx = 0.5 * (a.gx0 + a.gx1), cy = 0.5 * (a.gy0 + a.gy1);
             lref[c] = hypot(cx - chan[4 * c], cy - chan[4 * c + 1]) + hypot(cx - chan[4 * c + 2], cy - chan[4 * c + 3]);
+        } else if (idx < n1) {
+            const int kap = static_cast<int>(idx - n0);
+            krz[kap] = kref_of(a, k, kap);
         } else if (idx < n2) {
             const int t = static_cast<int>(idx - n1);
             double s, c;
@@ -61,12 +84,11 @@ __global__ void plan_tables_kernel(PlanTablesArgs a, const double* __restrict__ 
         } else {
             const long long e = idx - n3;
             const int kap = static_cast<int>(e / a.n_f), f = static_cast<int>(e % a.n_f);
-            const int sk = kap < (a.n_z + 1) / 2 ? kap : kap - a.n_z;
-            const double kz = 2.0 * kPi * sk / (a.n_z * a.scan_step);
+            const double kz = kz_of(kap, a.n_z, a.scan_step);
             const double arg = k[f] * k[f] - 0.25 * kz * kz;
             const bool valid = arg > 0.0;
             const double kr = valid ? sqrt(arg) : 0.0;
-            const double kpr = kr - a.kref[kap / a.block];
+            const double kpr = kr - kref_of(a, k, kap);
             kp[e] = kpr;
             double w = valid ? k[f] : 0.0;
             if (valid && a.interp == PL_INTERP_BSPLINE4) {
@@ -384,6 +406,7 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
     a.interp = p.interp;
     a.n_gl = p.n_gl;
     a.block = p.block;
+    a.ref_mode = p.ref_mode;
     a.du = p.du;
     a.h = p.h;
     a.beta = p.beta;
@@ -397,16 +420,17 @@ int launch_plan_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
         a.glw[q] = p.gl_w[q];
     }
     a.scan_step = p.scan_step;
-    const long long total = static_cast<long long>(p.n_ch) + p.n_fine + p.n_l +
+    const long long total = static_cast<long long>(p.n_ch) + p.n_z + p.n_fine + p.n_l +
                             static_cast<long long>(p.n_z) * p.n_f;
     const int blocks = static_cast<int>(std::min<long long>((total + 255) / 256, 4096));
     hipLaunchKernelGGL(plan_tables_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan, dt.k,
                        reinterpret_cast<double*>(ws + p.off_llo), reinterpret_cast<double*>(ws + p.off_lref),
                        reinterpret_cast<float2*>(ws + p.off_tw_fine), reinterpret_cast<float*>(ws + p.off_deap),
-                       reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk));
+                       reinterpret_cast<double*>(ws + p.off_kp), reinterpret_cast<float*>(ws + p.off_wk),
+                       reinterpret_cast<double*>(ws + p.off_krz));
     int rc = check_launch("plan tables");
     if (!rc) rc = launch_axis_fft_tables(p.zfft, ws + p.off_zfft, s);
-    return rc ? rc : launch_gather_tables(p, dt, ws, s);
+    return rc ? rc : launch_tile_tables(p, dt, ws, s);
 }
 
 int launch_axis_fft_tables(const AxisFft& f, char* tables, hipStream_t s) {

@@ -74,6 +74,19 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         p.force_tile_y = opts->tile_y;
         p.force_kb = opts->kz_block;
         p.range_method = opts->range_method;
+        p.ref_mode = opts->ref_mode;
+    }
+    if (p.ref_mode != PL_REF_BAND_CENTRE && p.ref_mode != PL_REF_MIN_K)
+        return fail(PL_EINVAL, "unknown ref_mode %d", p.ref_mode);
+    if (p.ref_mode == PL_REF_MIN_K) {
+        // the paper's reference differs per k_z bin: its carrier is formed per
+        // term, which only the k_z-per-lane back-projection does
+        if (p.range_method != PL_RANGE_NUFFT)
+            return fail(PL_EUNSUPPORTED, "ref_mode PL_REF_MIN_K takes the NUFFT range compression");
+        if (p.force_bp_mfma > 0)
+            return fail(PL_EUNSUPPORTED, "ref_mode PL_REF_MIN_K takes the VALU back-projection");
+        if (p.force_kpl > 1 || p.force_kb != 0 || (p.force_waves != 0 && p.force_waves != 4))
+            return fail(PL_EUNSUPPORTED, "ref_mode PL_REF_MIN_K runs one k_z bin per lane, 4 wavefronts");
     }
     if (p.force_kpl != 0 && p.force_kpl != 1 && p.force_kpl != 2 && p.force_kpl != 4)
         return fail(PL_EINVAL, "kz_per_lane must be 0, 1, 2 or 4");
@@ -131,6 +144,26 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
                 half_band = std::max(half_band, 0.5 * (hi - lo));
             }
         }
+        if (p.ref_mode == PL_REF_MIN_K) {
+            // the paper's k_rho0 = k_rho at the lowest wavenumber k_0 (the
+            // smallest real k_rho of the bin where k_0 is evanescent): k' runs
+            // over [0, max k_rho - k_rho0], so the range grid resolves the
+            // widest such band
+            half_band = 0.0;
+            for (int kap = 0; kap < p.n_z; ++kap) {
+                const int sk = kap < (p.n_z + 1) / 2 ? kap : kap - p.n_z;
+                const double kz = 2.0 * kPi * sk / (p.n_z * g->scan_step);
+                double lo = -1.0, hi = -1.0;
+                for (int f = 0; f < p.n_f; ++f) {
+                    const double arg = g->k[f] * g->k[f] - 0.25 * kz * kz;
+                    if (arg <= 0) continue;
+                    const double kr = std::sqrt(arg);
+                    if (lo < 0) lo = kr;
+                    hi = kr;
+                }
+                if (lo >= 0) half_band = std::max(half_band, hi - lo);
+            }
+        }
         if (half_band <= 0) half_band = 1.0;  // single frequency, no k_z spread
         p.half_band = half_band;
         p.sigma_used = sigma;
@@ -141,7 +174,11 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     // each group's taps inside one 16-sample window that starts on a multiple
     // of 4 samples.  |l(p) - l(q)| <= 2 |p - q|, so a group's first tap is at
     // most 3 samples past its window start and its last at most
-    // ceil(2 * diagonal / du) + 3 past its first.
+    // ceil(2 * diagonal / du) + 3 past its first.  The kernel forms each
+    // pixel's position in float32 from its tile centre's (error far below
+    // 1e-3 samples), so the plan keeps 2 * diagonal / du <= 8.99: a floor
+    // taken in float32 then never spreads a group's first taps over more
+    // than 9 samples.
     p.bp_mfma = false;
     p.bp_mfma_sp = false;
     if (p.force_bp_mfma > 2) return fail(PL_EINVAL, "mfma_backprojection must be -1, 0, 1 or 2");
@@ -164,18 +201,19 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         // with 64 k_z bins: measured fastest on gfx950
         const double gdiag = std::hypot(3.0 * grid->dx, 3.0 * grid->dy);
         set_blocks(kb, p.sigma_l);
-        if (std::ceil(2.0 * gdiag / p.du) > 9) {
+        if (2.0 * gdiag / p.du > 8.99) {
             // widest grid step that fits, as long as the oversampling stays >= 4
-            const double du_fit = 2.0 * gdiag / 8.999;
+            const double du_fit = 2.0 * gdiag / 8.99;
             const double sigma_fit = kPi / (du_fit * p.half_band);
             if (sigma_fit >= 4.0) set_blocks(kb, std::min(p.sigma_l, sigma_fit));
         }
-        // staged window: every tap of the tile plus alignment (8-sample chunks)
+        // staged window: every tap of the tile plus alignment (8-sample
+        // chunks), and one sample against float rounding
         const double rt = 0.5 * std::hypot((tx - 1) * grid->dx, (ty - 1) * grid->dy);
-        const int need = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 6;
+        const int need = static_cast<int>(std::ceil(4.0 * rt / p.du)) + 7;
         const int nck = std::max(2, (need + 7) / 8);
-        const size_t lds = backproject_mfma_lds_bytes(p.n_ch, kb, sp);
-        if (std::ceil(2.0 * gdiag / p.du) <= 9 && nck <= 8 && lds <= kMaxLds && p.n_f <= 128) {
+        const size_t lds = backproject_mfma_lds_bytes(kb, sp);
+        if (2.0 * gdiag / p.du <= 8.995 && nck <= 8 && lds <= kMaxLds && p.n_f <= 128) {
             p.bp_mfma = true;
             p.bp_mfma_sp = sp;
             p.tile_x = tx;
@@ -205,7 +243,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         if (p.force_kb && (p.force_kb > 64 || p.force_kpl))
             return fail(PL_EINVAL, "the VALU back-projection takes kz_block 32 or 64 (pixel-per-lane kernel)");
         if (p.force_kpl == 0 && (p.force_tile == 0 || p.force_tile == 8) &&
-            (p.force_waves == 0 || p.force_waves == 4)) {
+            (p.force_waves == 0 || p.force_waves == 4) && p.ref_mode == PL_REF_BAND_CENTRE) {
             // staged rows start on an even sample (16-byte copies) and hold
             // the window: the taps of every pixel of the 8x8 tile and the
             // sample after them (a pixel reads three aligned chunks around
@@ -361,7 +399,8 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_deap = take(static_cast<size_t>(p.n_l) * 4);
     p.off_kp = take(nz * nf * 8);
     p.off_wk = take(nz * nf * 4);
-    p.off_tiles = take(p.bp_gather ? gather_table_bytes(p) : 0);
+    p.off_krz = take(nz * 8);
+    p.off_tiles = take(tile_table_bytes(p));
     p.n_chp = (p.n_ch + 31) / 32 * 32;
     p.n_fp = (p.n_f + 15) / 16 * 16;
     if (p.precision != PL_PREC_FP32) {

@@ -146,6 +146,31 @@ def test_plan_blocks_and_transform_length_at_any_scan_length(n_scan):
     assert pr.fft_workspace_bytes(g) >= 8 * want_len * (1 if _smooth(n_scan) else 3)
 
 
+def test_reference_mode_plans():
+    # PL_REF_MIN_K: the paper's per-k_z reference k_rho0 = k_rho(k_0): every
+    # k' lies in [0, max k_rho - k_rho0], so the range step follows the
+    # widest such band at the requested oversampling, on the k_z-per-lane
+    # kernel; options it cannot run are refused
+    for wl in (W.C1, W.C2, W.C3):
+        a = wl.array
+        g = pr.make_geometry(a)
+        p = pr.hybrid_plan_info(g, wl.grid, ref_mode="min-k")
+        assert p.bp_kernel == "kz-lanes" and p.block == 64
+        kz = 2 * np.pi * np.fft.fftfreq(a.n_scan, a.scan_step)
+        kf = 2 * np.pi * np.linspace(a.f_start, a.f_stop, a.n_freq) / W.SPEED_OF_LIGHT
+        kr2 = kf[None] ** 2 - kz[:, None] ** 2 / 4
+        band = max(np.sqrt(r[r > 0]).max() - np.sqrt(r[r > 0]).min() for r in kr2 if (r > 0).any())
+        assert math.isclose(p.du, math.pi / (6 * band), rel_tol=1e-12)
+    g = pr.make_geometry(W.C1.array)
+    for bad in (dict(range_method="resample"), dict(precision="bf16", mfma_backprojection=1),
+                dict(kz_per_lane=2), dict(kz_block=32), dict(waves=8)):
+        with pytest.raises(pr.PolyreconError) as e:
+            pr.hybrid_plan_info(g, W.C1.grid, ref_mode="min-k", **bad)
+        assert e.value.code == pr.PL_EUNSUPPORTED, bad
+    with pytest.raises(ValueError):
+        pr.hybrid_plan_info(g, W.C1.grid, ref_mode="centre")
+
+
 def test_sampling_criteria():
     # C1's half-wavelength transceivers satisfy eq. (21)/2; doubling the
     # spacing or the scan step beyond eq. (22) raises the warnings.
@@ -178,6 +203,10 @@ def test_raw_abi_argument_errors_before_device_use():
     assert L.reconstruct_bp(g.handle, grid, 0, 0, fake, fake, fake, 1 << 30, None) == pr.PL_EINVAL
     assert L.reconstruct_bp(g.handle, grid, 20, 10, fake, fake, fake, 1 << 30, None) == pr.PL_EINVAL
     assert L.reconstruct_bp(g.handle, grid, 0, 1, fake, fake, fake, 16, None) == pr.PL_EWORKSPACE
+    bneed = pr.bp_workspace_bytes(g, W.C1.grid, 2)
+    assert bneed >= 8 * W.C1.array.n_channels * W.C1.array.n_scan * W.C1.array.n_freq
+    assert L.reconstruct_bp(g.handle, grid, 0, 2, fake, fake, fake, bneed - 1, None) == pr.PL_EWORKSPACE
+    assert L.reconstruct_bp(g.handle, grid, 0, 2, fake, fake, C.c_void_p((1 << 20) + 8), bneed, None) == pr.PL_EWORKSPACE
     assert L.simulate_echo(g.handle, -1, fake, fake, fake, None) == pr.PL_EINVAL
     assert L.simulate_echo(g.handle, 3, None, fake, fake, None) == pr.PL_EINVAL
     assert L.scan_fft(None, fake, fake, fake, 1 << 20, None) == pr.PL_EINVAL

@@ -447,6 +447,30 @@ def test_hybrid_scan_lengths_that_are_not_smooth(case, n_scan):
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("case", ["C1", "multi-small", "evanescent-small", "tiny-mono-fine"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_reference_wavenumber_modes_give_the_same_image(case, precision):
+    # eqs. (8a)/(8b) and (19a)/(19b): the reference wavenumber cancels, so the
+    # paper's k_rho0 = k_rho at the lowest k (per k_z bin) and the band-centre
+    # reference per block both reach the exact sum within the FP32 bar; in
+    # "evanescent-small" k_0 is evanescent in some bins (the smallest real
+    # k_rho of the bin is the reference there)
+    wl = {"C1": W.C1, "multi-small": multi_small(), "evanescent-small": evanescent_small(),
+          "tiny-mono-fine": W.tiny("mono")}[case]
+    grid = _fine_grid(37, 29, 0.004) if case == "tiny-mono-fine" else wl.grid
+    g = pr.make_geometry(wl.array)
+    arr = ogeom.build(wl.array)
+    s = W.random_echo(wl.array, 23)
+    ref = ohyb.image(arr, grid, s)
+    assert pr.hybrid_plan_info(g, grid, precision=precision, ref_mode="min-k").bp_kernel == "kz-lanes"
+    errs = []
+    for mode in ("band-centre", "min-k"):
+        img = host(pr.reconstruct_hybrid(g, grid, dev(s), precision=precision, ref_mode=mode))
+        errs.append(rel(img, ref))
+    say("reference modes", case, precision, "band-centre %.2e, min-k %.2e" % tuple(errs))
+    assert max(errs) < 1e-4
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (9, 13), (17, 5), (64, 40)])
 def test_hybrid_ragged_grids(nx, ny):
     wl = W.tiny("multi")
