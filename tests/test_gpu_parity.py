@@ -790,7 +790,7 @@ def test_autograd_gradients_against_oracle_and_finite_differences():
 
 
 @pytest.mark.parametrize("method", ["cg", "sd"])
-def test_least_squares_refinement(method):
+def test_least_squares_refinement(method, tmp_path):
     from paper_2109_02842_amd import autograd as ag
     desc, grid = _adjoint_case("C1")
     g = pr.make_geometry(desc)
@@ -806,6 +806,13 @@ def test_least_squares_refinement(method):
     assert len(hist) == 11
     assert all(b <= a * (1 + 1e-6) for a, b in zip(hist, hist[1:]))
     assert hist[-1] < 0.5 * hist[0]
+    # interrupted after 4 steps, resumed from the checkpoint: the same
+    # iterate bit for bit (deterministic kernels, same operation order)
+    ck = str(tmp_path / f"refine-{method}.pt")
+    ag.refine(g, grid, dev(s), steps=4, method=method, checkpoint=ck)
+    x2, hist2 = ag.refine(g, grid, dev(s), steps=10, method=method, checkpoint=ck, resume=True)
+    assert hist2 == hist
+    assert np.array_equal(host(x2).view(np.uint32), host(x).view(np.uint32))
 
 
 # ------------------------------------------------ omega-K variant (resampling)
