@@ -28,6 +28,7 @@ constexpr int kProfileScaleParts = 64;
 constexpr size_t kMaxLds = 160 * 1024;          // LDS per workgroup on gfx950
 constexpr int kMaxFreq = 1024;
 constexpr int kMaxFine = 4096;      // NUFFT fine grid held twice in LDS (64 KiB)
+constexpr double kNufftUpsample = 1.25;  // FP32 NUFFT: fine grid of at least 1.25 n_l points
 constexpr int kMaxGL = 64;          // quadrature nodes for the kernel transform
 constexpr int kMaxRadices = 16;
 

@@ -318,27 +318,34 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.tiles_x = (grid->nx + p.tile_x - 1) / p.tile_x;
     p.tiles_y = (grid->ny + p.tile_y - 1) / p.tile_y;
 
-    // range samples: a multiple of 4 (8-byte stores of split BF16 profiles)
-    // with a 2,3,5-smooth fine grid of 2 n_l.  The FP32 range compressions
-    // have a wavefront-per-pair kernel for fine grids of 64 R points (R
-    // 2,3,5-smooth, at most 32), about twice as fast per point as the
-    // workgroup kernel: n_l = 32 R when that adds at most a quarter.
+    // range samples: a multiple of 4 (8-byte stores of split BF16 profiles).
+    // The NUFFT's fine grid: for FP32 NUFFT plans the smallest grid of at
+    // least 1.25 n_l points, preferring the 64 R sizes (R 2,3,5-smooth, at
+    // most 32) of the wavefront-per-pair kernels; other plans keep 2 n_l
+    // (2,3,5-smooth; the resampling method's uniform grid and the plan
+    // tables use it).
     int nl = static_cast<int>(std::ceil(span / p.du)) + 8;
     nl = std::max(nl, p.window + 2);
     nl = (nl + 3) & ~3;
-    const int nl_min = nl;
-    while (!is_fft_friendly(2 * nl)) nl += 4;
-    if (p.precision == PL_PREC_FP32) {
-        for (int r = (nl_min + 31) / 32; r <= 32; ++r)
-            if (is_fft_friendly(r)) {
-                if (32 * r <= nl_min + nl_min / 4) nl = 32 * r;
-                break;
+    const bool nufft32 = p.precision == PL_PREC_FP32 && p.range_method == PL_RANGE_NUFFT;
+    if (nufft32) {
+        const int want = static_cast<int>(std::ceil(kNufftUpsample * nl));
+        int nf = 0;
+        for (int r = (want + 63) / 64; r <= 32 && !nf; ++r)
+            if (is_fft_friendly(r)) nf = 64 * r;
+        if (!nf)
+            for (nf = want; !is_fft_friendly(nf); ++nf) {
             }
+        p.n_l = nl;
+        p.n_fine = nf;
+    } else {
+        while (!is_fft_friendly(2 * nl)) nl += 4;
+        p.n_l = nl;
+        p.n_fine = 2 * nl;
     }
-    p.n_l = nl;
-    p.n_fine = 2 * nl;
     if (p.n_fine > kMaxFine)
-        return fail(PL_EUNSUPPORTED, "range grid of %d samples exceeds %d (lower l_oversample)", nl, kMaxFine / 2);
+        return fail(PL_EUNSUPPORTED, "range grid of %d samples needs a fine grid over %d (lower l_oversample)", p.n_l,
+                    kMaxFine);
     factor_radices(p.n_fine, &p.fine_rad);
     if (p.range_method == PL_RANGE_RESAMPLE) {
         // uniform k_L grid whose inverse FFT lands on the range grid: step
@@ -356,13 +363,23 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
         for (int b = 0; b < p.n_blocks; ++b) p.kref[b] = p.dkl * std::nearbyint(p.kref[b] / p.dkl);
     }
 
-    // Exponential-of-semicircle kernel (Barnett, Magland, af Klinteberg 2019)
-    // for a 2x oversampled fine grid: width W = ceil(log10(1/tol)) + 1,
-    // shape beta = 2.30 W.
-    p.W = std::max(2, static_cast<int>(std::ceil(std::log10(1.0 / p.tol))) + 1);
-    p.W = std::min(p.W, 16);
+    // Exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) of
+    // width W (Barnett, Magland, af Klinteberg 2019).  For the 2x fine grid:
+    // W = ceil(log10(1/tol)) + 1, beta = 2.30 W.  For an upsampling factor
+    // s = n_fine / n_l below 2, their error estimate exp(-pi W sqrt(1 - 1/s))
+    // gives W = ceil(ln(1/tol) / (pi sqrt(1 - 1/s))), and beta =
+    // 0.97 pi W (1 - 1/(2 s)).
+    const double ups = static_cast<double>(p.n_fine) / p.n_l;
+    if (ups >= 1.999) {
+        p.W = std::max(2, static_cast<int>(std::ceil(std::log10(1.0 / p.tol))) + 1);
+        p.W = std::min(p.W, 16);
+        p.beta = 2.30 * p.W;
+    } else {
+        p.W = std::max(2, static_cast<int>(std::ceil(std::log(1.0 / p.tol) / (kPi * std::sqrt(1.0 - 1.0 / ups)))));
+        p.W = std::min(p.W, 16);
+        p.beta = 0.97 * kPi * p.W * (1.0 - 0.5 / ups);
+    }
     p.h = 0.5 * p.W;
-    p.beta = 2.30 * p.W;
     if (p.n_fine / p.sigma_l + 2 * p.W + 2 >= p.n_fine) return fail(PL_EUNSUPPORTED, "fine grid too short");
     p.n_gl = std::min(kMaxGL, 4 * p.W + 16);
     gauss_legendre(p.n_gl, p.gl_x, p.gl_w);

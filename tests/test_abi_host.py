@@ -72,8 +72,12 @@ def test_plan_is_consistent(wl):
     g = pr.make_geometry(wl.array)
     p = pr.hybrid_plan_info(g, wl.grid)
     assert p.n_kz == wl.array.n_scan
-    assert p.n_fine == 2 * p.n_l and p.n_l % 2 == 0
-    assert p.kernel_width == 7                      # 1e-6 tolerance
+    # FP32 NUFFT fine grid: at least 1.25 n_l points, 2,3,5-smooth, kernel
+    # width from the error estimate exp(-pi W sqrt(1 - 1/s)) <= 1e-6
+    ups = p.n_fine / p.n_l
+    assert ups >= 1.25 and p.n_l % 4 == 0 and _smooth(p.n_fine)
+    assert p.kernel_width == math.ceil(math.log(1e6) / (math.pi * math.sqrt(1 - 1 / ups)))
+    assert math.isclose(p.beta, 0.97 * math.pi * p.kernel_width * (1 - 0.5 / ups), rel_tol=1e-12)
     assert p.block % 32 == 0
     assert p.n_blocks == math.ceil(wl.array.n_scan / p.block)
     # the range grid covers every channel's range span at the requested step
@@ -359,8 +363,10 @@ def test_resample_range_method_plan_rules():
     assert p.range_method == "resample"
     # the inverse FFT of the uniform grid lands on the range grid
     assert p.dk_uniform == pytest.approx(2 * math.pi / (p.n_fine * p.du), rel=1e-12)
-    # same range grid and back-projection as the NUFFT plan
-    assert (p.n_l, p.du, p.bp_kernel, p.block) == (base.n_l, base.du, base.bp_kernel, base.block)
+    # same range step and back-projection as the NUFFT plan; its range grid
+    # is rounded up to a 2,3,5-smooth fine grid of 2 n_l points
+    assert (p.du, p.bp_kernel, p.block) == (base.du, base.bp_kernel, base.block)
+    assert p.n_l >= base.n_l and p.n_fine == 2 * p.n_l and _smooth(p.n_fine)
     # reference wavenumbers moved onto the grid (by at most half a step)
     for kr, kb in zip(p.k_ref, base.k_ref):
         assert abs(kr / p.dk_uniform - round(kr / p.dk_uniform)) < 1e-9

@@ -195,14 +195,15 @@ def _oversampling_for_fine_grid(g, grid, n_fine):
     raise AssertionError(f"no oversampling gives a {n_fine}-point fine grid")
 
 
-@pytest.mark.parametrize("radix", [4, 5, 9, 10, 16, 18, 20, 25, 27, 30, 32, 36])
-def test_range_compress_every_wavefront_radix(radix):
+@pytest.mark.parametrize("n_fine", [64 * r for r in (3, 4, 5, 6, 9, 10, 16, 18, 20, 24, 25, 27, 30, 32)] + [2160])
+def test_range_compress_every_wavefront_radix(n_fine):
     # C1 at the oversampling that makes the fine grid 64 R points: every
-    # R-point register DFT the wavefront NUFFT is compiled for that the
-    # workloads do not reach (R = 36 is past them: the workgroup kernel)
+    # R-point register DFT the wavefront NUFFT is compiled for (2160 points
+    # are past them: the workgroup kernel)
     wl = W.C1
     g = pr.make_geometry(wl.array)
-    sig, plan = _oversampling_for_fine_grid(g, wl.grid, 64 * radix)
+    sig, plan = _oversampling_for_fine_grid(g, wl.grid, n_fine)
+    radix = n_fine // 64
     say("range_compress radix", radix, "l_oversample", sig, "n_l", plan.n_l)
     s = W.random_echo(wl.array, 30 + radix)
     spec = pr.scan_fft(g, dev(s))
