@@ -494,7 +494,10 @@ def bench_batch(args, torch, pr, W) -> int:
         echoes.append(pr.simulate_echo(g, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda()))
     torch.cuda.synchronize()
     opts = dict(precision=args.precision)
-    batch = pr.HybridBatch(geoms, [w.grid for w in wls], opts)
+    # per-scan launch shapes from the autotuner (timed on the device here)
+    t0 = time.perf_counter()
+    batch = pr.HybridBatch.autotuned(geoms, [w.grid for w in wls], args.precision, echoes=echoes, repeats=3)
+    tune_s = time.perf_counter() - t0
     voxels = sum(w.array.n_scan * w.grid.nx * w.grid.ny for w in wls)
     terms = sum(w.array.n_scan * w.grid.nx * w.grid.ny * g.n_channels for w, g in zip(wls, geoms))
     log(f"[bench] C5: {len(wls)} scans, {voxels:.3e} voxels; persistent back-projection: "
@@ -518,11 +521,11 @@ def bench_batch(args, torch, pr, W) -> int:
     bws = pr.workspace(batch.workspace_bytes)
     outs = [torch.empty_like(o) for o in cap.outs]
     ms_call = timed(lambda: pr.reconstruct_hybrid_batch(batch, echoes, outs, bws), args.steps, 1)
-    wss = [pr.workspace(pr.hybrid_workspace_bytes(g, w.grid, **opts)) for g, w in zip(geoms, wls)]
+    wss = [pr.workspace(pr.hybrid_workspace_bytes(g, w.grid, **so)) for g, w, so in zip(geoms, wls, batch.opts)]
 
     def singles():
-        for g, w, e, o, ws in zip(geoms, wls, echoes, outs, wss):
-            pr.reconstruct_hybrid(g, w.grid, e, out=o, ws=ws, **opts)
+        for g, w, e, o, ws, so in zip(geoms, wls, echoes, outs, wss, batch.opts):
+            pr.reconstruct_hybrid(g, w.grid, e, out=o, ws=ws, **so)
 
     ms_single = timed(singles, args.steps, 1)
     log(f"[bench] C5: graph replay {ms:.3f} ms, batch call {ms_call:.3f} ms, 16 separate calls {ms_single:.3f} ms")
@@ -540,7 +543,9 @@ def bench_batch(args, torch, pr, W) -> int:
                      "flop_per_launch": FLOP_PER_TERM * terms, "avg_launch_ms": ms},
         "batch": {"scans": len(wls), "queued_scans": batch.queued_scans, "work_items": batch.work_items,
                   "workgroups": batch.workgroups, "ms_graph_replay": ms, "ms_batch_call": ms_call,
-                  "ms_separate_calls": ms_single},
+                  "ms_separate_calls": ms_single, "autotune_s": tune_s,
+                  "scan_lengths": [w.array.n_scan for w in wls],
+                  "tuned_options": [{k: v for k, v in o.items() if k != "precision"} for o in batch.opts]},
     }
     if not args.no_parity:
         from oracle import geometry as ogeom

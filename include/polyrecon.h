@@ -491,9 +491,13 @@ int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spe
  * allocation owned by the batch; use the batch on that device only).
  * reconstruct_hybrid_batch takes arrays of n device pointers: echoes
  * ([c][m][f] complex64 per scan) and images ([z][y][x] complex64 per scan),
- * and a 256-byte-aligned device workspace of hybrid_batch_info's size.  It
+ * and a 256-byte-aligned device workspace of hybrid_batch_info's size.  The
+ * per-scan steps of different scans run concurrently on up to four helper
+ * streams the batch owns (default priority, created by make_hybrid_batch),
+ * forked from and joined back into `stream` with events: the call's work
+ * starts after, and later work on `stream` waits for, all of it.  It
  * allocates nothing and does not synchronise, so it may be captured in a
- * graph; calls sharing one workspace must not overlap.
+ * graph; calls on one batch, or sharing one workspace, must not overlap.
  * hybrid_batch_info: workspace bytes, scans in the persistent launch, its
  * work items and workgroups (any pointer may be NULL).
  * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.

@@ -431,6 +431,16 @@ class HybridBatch:
         self.workspace_bytes = int(ws.value)
         self.queued_scans, self.work_items, self.workgroups = queued.value, items.value, wgs.value
 
+    @classmethod
+    def autotuned(cls, geoms, grids, precision: str = "fp32", echoes=None, cache: Optional[str] = None,
+                  repeats: int = 5, **fixed) -> "HybridBatch":
+        """A batch whose scans take the launch shapes the autotuner finds
+        fastest for each (timed per scan on the device, cached in ``cache``);
+        ``fixed`` options (e.g. the interpolation) apply to every scan."""
+        from .autotune import autotune_batch
+        opts = autotune_batch(geoms, grids, precision, echoes=echoes, cache=cache, repeats=repeats, **fixed)
+        return cls(geoms, grids, opts)
+
     def __len__(self):
         return len(self.geoms)
 

@@ -56,10 +56,23 @@ int plan_axis_fft(int n, AxisFft* out) {
     if (factor_radices(n, &f.rad)) {
         f.m = n;
     } else {
-        int m = 2 * n - 1;
-        while (m <= kMaxChirpLen && !factor_radices(m, &f.rad)) ++m;
-        if (m > kMaxChirpLen) return fail(PL_EUNSUPPORTED, "transform length %d needs a chirp-z length over %d", n, kMaxChirpLen);
-        f.m = m;
+        // any smooth m >= 2n - 1 serves; each radix stage is one pass through
+        // LDS with a barrier, so take the one with the least m x stages
+        // among those up to twice the smallest
+        int best = 0;
+        long long best_cost = 0;
+        Radices r;
+        for (int m = 2 * n - 1; m <= std::min(kMaxChirpLen, 2 * (2 * n - 1)); ++m) {
+            if (!factor_radices(m, &r)) continue;
+            const long long cost = static_cast<long long>(m) * r.count;
+            if (!best || cost < best_cost) {
+                best = m;
+                best_cost = cost;
+            }
+        }
+        if (!best) return fail(PL_EUNSUPPORTED, "transform length %d needs a chirp-z length over %d", n, kMaxChirpLen);
+        factor_radices(best, &f.rad);
+        f.m = best;
         f.chirp = true;
     }
     size_t off = 0;

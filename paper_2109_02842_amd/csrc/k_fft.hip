@@ -136,7 +136,7 @@ __global__ void axis_fft_tables_kernel(int n, int m, int chirp, float2* __restri
 struct FftArgs {
     int n, m, nbatch, inner, per_wg, ld, sign, n_fast_in, n_fast_out;
     long long in_so, in_si, in_sn, out_so, out_si, out_sn;
-    float scale, inv_inner;
+    float scale, inv_inner, inv_n, inv_m, inv_pad;   // reciprocals for div_small: 1/inner, 1/n, 1/m, 1/(m - n)
     Radices rad;
 };
 
@@ -205,22 +205,24 @@ __global__ __launch_bounds__(256) void fft_chirp_strided_kernel(const float2* __
     const int nb = min(a.per_wg, a.nbatch - b0);
     const int tid = threadIdx.x;
     const bool inv = a.sign > 0;
-    for (int e = tid; e < nb * (a.m - a.n); e += blockDim.x) {
-        const int t = e / (a.m - a.n);
-        A[t * a.ld + a.n + (e - t * (a.m - a.n))] = make_float2(0.f, 0.f);
+    const float inv_nb = 1.0f / nb;
+    const int pad = a.m - a.n;
+    for (int e = tid; e < nb * pad; e += blockDim.x) {
+        const int t = div_small(e, a.inv_pad);
+        A[t * a.ld + a.n + (e - t * pad)] = make_float2(0.f, 0.f);
     }
     const int total = nb * a.n;
     for (int e = tid; e < total; e += blockDim.x) {
         int t, i;
         if (a.n_fast_in) {
-            t = e / a.n;
+            t = div_small(e, a.inv_n);
             i = e - t * a.n;
         } else {
-            i = e / nb;
+            i = div_small(e, inv_nb);
             t = e - i * nb;
         }
         const int b = b0 + t;
-        const int o = b / a.inner, s = b - o * a.inner;
+        const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
         float2 v = in[o * a.in_so + s * a.in_si + i * a.in_sn];
         if (inv) v.y = -v.y;
         A[t * a.ld + i] = cmul(v, w[i]);
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) void fft_chirp_strided_kernel(const float2* __
     __syncthreads();
     float2* r = lds_fft(A, B, a.m, a.ld, nb, a.rad, tw, -1, tid, blockDim.x);
     for (int e = tid; e < nb * a.m; e += blockDim.x) {
-        const int t = e / a.m, i = e - t * a.m;
+        const int t = div_small(e, a.inv_m), i = e - t * a.m;
         r[t * a.ld + i] = cmul(r[t * a.ld + i], hat[i]);
     }
     __syncthreads();
@@ -236,14 +238,14 @@ __global__ __launch_bounds__(256) void fft_chirp_strided_kernel(const float2* __
     for (int e = tid; e < total; e += blockDim.x) {
         int t, i;
         if (a.n_fast_out) {
-            t = e / a.n;
+            t = div_small(e, a.inv_n);
             i = e - t * a.n;
         } else {
-            i = e / nb;
+            i = div_small(e, inv_nb);
             t = e - i * nb;
         }
         const int b = b0 + t;
-        const int o = b / a.inner, s = b - o * a.inner;
+        const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
         float2 v = cmul(r[t * a.ld + i], w[i]);
         if (inv) v.y = -v.y;
         out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(v, a.scale);
@@ -358,11 +360,18 @@ int run_fft(const float2* in, float2* out, const AxisFft& f, const char* tables,
     a.out_sn = out_sn;
     a.scale = scale;
     a.inv_inner = 1.0f / inner;
+    a.inv_n = 1.0f / f.n;
+    a.inv_m = 1.0f / f.m;
+    a.inv_pad = f.m > f.n ? 1.0f / (f.m - f.n) : 1.0f;
     a.rad = f.rad;
     if (nbatch <= 0) return PL_OK;
     if (nbatch > (1LL << 31) - 1) return fail(PL_EUNSUPPORTED, "%s: too many transforms", what);
     const float2* tw = reinterpret_cast<const float2*>(tables + f.off_tw);
     if (f.chirp) {
+        // the chirp kernel splits indices with float reciprocals (div_small):
+        // exact while index + divisor < 2^22
+        if (nbatch + inner >= (1LL << 22))
+            return fail(PL_EUNSUPPORTED, "%s: %lld chirp-z transforms exceed the index range", what, nbatch);
         const size_t smem = 2ull * a.per_wg * a.ld * sizeof(float2);
         int rc = set_lds_limit(reinterpret_cast<const void*>(fft_chirp_strided_kernel), smem, what);
         if (rc) return rc;

@@ -120,6 +120,16 @@ def test_plan_errors():
         pr.hybrid_plan_info(g, W.C1.grid, precision="fp64")
 
 
+def _stages(m):
+    """Radix stages of a 2,3,5-smooth length: factors of 8, then 4, 2, 3, 5."""
+    count = 0
+    for r in (8, 4, 2, 3, 5):
+        while m % r == 0:
+            m //= r
+            count += 1
+    return count
+
+
 def _smooth(n):
     for p in (2, 3, 5):
         while n % p == 0:
@@ -145,9 +155,14 @@ def test_plan_blocks_and_transform_length_at_any_scan_length(n_scan):
             kr = np.sqrt(kr2[kr2 > 0])
             want = 0.5 * (kr.min() + kr.max()) if kr.size else 0.0
             assert math.isclose(p.k_ref[b], want, rel_tol=1e-12, abs_tol=1e-9)
-        want_len = n_scan if _smooth(n_scan) else min(m for m in range(2 * n_scan - 1, 4 * n_scan) if _smooth(m))
+        # smooth lengths run as they are; any other through the chirp-z
+        # length >= 2n - 1 (up to twice that) with the fewest length x stages
+        lo = 2 * n_scan - 1
+        want_len = n_scan if _smooth(n_scan) else min((m for m in range(lo, 2 * lo + 1) if _smooth(m)),
+                                                       key=lambda m: (m * _stages(m), m))
         assert p.scan_fft_len == want_len
     assert pr.fft_workspace_bytes(g) >= 8 * want_len * (1 if _smooth(n_scan) else 3)
+    assert _smooth(want_len) and want_len >= (n_scan if _smooth(n_scan) else 2 * n_scan - 1)
 
 
 def test_reference_mode_plans():

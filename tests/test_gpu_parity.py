@@ -688,6 +688,27 @@ def test_batch_graph_replays():
         del junk
 
 
+def test_autotuned_batch_matches_single_scans(tmp_path):
+    # per-scan tuned launch shapes (timed on the device, cached): the batch
+    # call equals single-scan calls with the same options bit for bit and
+    # the oracle within the FP32 bar
+    scans = _small_batch()[:3]
+    geoms = [pr.make_geometry(a) for a, _, _ in scans]
+    grids = [g for _, g, _ in scans]
+    cache = str(tmp_path / "tune.json")
+    batch = pr.HybridBatch.autotuned(geoms, grids, cache=cache, repeats=2)
+    say("autotuned batch options", batch.opts)
+    assert os.path.exists(cache)
+    echoes = [dev(W.random_echo(a, 300 + i)) for i, (a, _, _) in enumerate(scans)]
+    outs = pr.reconstruct_hybrid_batch(batch, echoes)
+    for i, g in enumerate(geoms):
+        single = host(pr.reconstruct_hybrid(g, grids[i], echoes[i], **batch.opts[i]))
+        assert np.array_equal(host(outs[i]).view(np.uint32), single.view(np.uint32)), i
+    a, grid, _ = scans[0]
+    ref = ohyb.image(ogeom.build(a), grid, W.random_echo(a, 300))
+    assert rel(host(outs[0]), ref) < 1e-4
+
+
 def test_autotune_picks_a_valid_configuration(tmp_path):
     from paper_2109_02842_amd import autotune as at
     wl = W.C1
