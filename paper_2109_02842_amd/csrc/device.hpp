@@ -19,6 +19,11 @@ __device__ __forceinline__ float2 cmul_i(float2 a, int sgn) {
     return sgn > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
+// v broadcast from lane `lane` of the wavefront (wavefront-uniform result).
+__device__ __forceinline__ float rdl(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // exp(j 2 pi x) for |x| <= 256 revolutions by the hardware sine and cosine
 // (v_sin_f32 / v_cos_f32 take revolutions; measured on gfx950: absolute error
 // at most 1.3e-7 over [-8, 8]).
