@@ -46,8 +46,9 @@ def test_bp_linearity():
 
 def test_bp_focuses_c1_targets_like_the_hybrid_method():
     # Independent route to the same scene: BP and the hybrid image must peak
-    # at the same voxels, and their magnitudes must agree in shape (the
-    # paper: "the focusing property ... is very similar to that of BP").
+    # at the same voxels, and their magnitudes must agree in shape (Sec. III
+    # compares the two methods' focusing on simulated point targets and finds
+    # them close).
     wl = W.C1
     arr = geometry.build(wl.array)
     pos, refl = W.scatterers(wl.scene)
