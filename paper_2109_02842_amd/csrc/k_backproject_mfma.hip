@@ -232,13 +232,17 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
-        // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
+                // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
         // each group and channel c0 + k: its range from the tile table
         // (float64 centre, float32 offset), its position in the group's
         // 16-sample window and its carrier; the MFMA lanes (pn, kg) of
-        // channel c0 + cc read them from lane 16 cc + pn.
+        // channel c0 + cc read them from lane 16 cc + pn.  The single-pass
+        // form also forms the pixel's four tap weights times the carrier
+        // here, packed to FP16 (P = w Re c, Q = w Im c), once per (pixel,
+        // channel) instead of once per MFMA lane.
         float xw[GPW], crw[GPW], ciw[GPW];
-        int srw[GPW];
+        unsigned pw0[GPW], pw1[GPW], qw0[GPW], qw1[GPW];
+        int dw[GPW], srw[GPW];
         {
             const int c = min(c0 + (lane >> 4), a.n_ch - 1);
             const GatherTileEntry e = tt[c];
@@ -264,12 +268,27 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                 m = min(m, __shfl_xor(m, 4));
                 m = min(m, __shfl_xor(m, 8));
                 const int sr = m == 0x3fffffff ? 0 : max(0, min(m & ~3, wpl - 16));
-                srw[g] = sr;
-                // position in the group window: floor(x) - 1 is the first tap
-                xw[g] = ok ? static_cast<float>(i0 - sr + 1) + (uu - fv) : 1000.f;
+                                srw[g] = sr;
                 const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
-                crw[g] = ok ? cc0.x * c1.x - cc0.y * c1.y : 0.f;
-                ciw[g] = ok ? cc0.x * c1.y + cc0.y * c1.x : 0.f;
+                const float cr = ok ? cc0.x * c1.x - cc0.y * c1.y : 0.f;
+                const float ci = ok ? cc0.x * c1.y + cc0.y * c1.x : 0.f;
+                if constexpr (SP) {
+                    const float t = uu - fv;
+                    float w[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
+                    pw0[g] = pack_f16(w[0] * cr, w[1] * cr);
+                    pw1[g] = pack_f16(w[2] * cr, w[3] * cr);
+                    qw0[g] = pack_f16(w[0] * ci, w[1] * ci);
+                    qw1[g] = pack_f16(w[2] * ci, w[3] * ci);
+                    dw[g] = ok ? i0 - sr : 1000;   // first tap in the group window
+                } else {
+                    // position in the group window: floor(x) - 1 is the first tap
+                    xw[g] = ok ? static_cast<float>(i0 - sr + 1) + (uu - fv) : 1000.f;
+                    crw[g] = cr;
+                    ciw[g] = ci;
+                }
             }
         }
 #pragma unroll 1
@@ -289,44 +308,59 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
             const int src = cc * 16 + pn;
 #pragma unroll
             for (int g = 0; g < GPW; ++g) {
-                // B operand: taps of this lane's pixel times the carrier,
-                // placed at its 8 samples by byte permutes
-                const float xn = __shfl(xw[g], src), crn = __shfl(crw[g], src), cin = __shfl(ciw[g], src);
                 const int sr = __builtin_amdgcn_readlane(srw[g], cc * 16);
-                const float fl = floorf(xn);
-                const float t = xn - fl;
-                // a0 = 4h - d0 with d0 = floor(x) - 1 the first tap in the group window
-                const int a0 = min(max(4 * h + 1 - static_cast<int>(fl), -15), 4);
-                const u32x4 sel = sel_tab[a0 + 15];
-                float w[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
-                const float ca = kg < 2 ? crn : -cin;  // rows of Re Q: Re B (Re G), Im B (Im G)
-                const float cb = kg < 2 ? cin : crn;   // rows of Im Q: -Im B, Re B
-                const float r0 = w[0] * ca, r1 = w[1] * ca, r2 = w[2] * ca, r3 = w[3] * ca;
-                const float i0 = w[0] * cb, i1 = w[1] * cb, i2 = w[2] * cb, i3 = w[3] * cb;
                 const unsigned char* ap = smem + bufo + a_lane + 2u * static_cast<unsigned>(sr);
                 if constexpr (SP) {
-                    const unsigned rh0 = pack_f16(r0, r1), rh1 = pack_f16(r2, r3);
-                    const unsigned ih0 = pack_f16(i0, i1), ih1 = pack_f16(i2, i3);
+                                        // B operand: the pixel's packed taps times the carrier,
+                    // placed at this lane's 8 samples by byte permutes.  Rows
+                    // of Re Q (kg < 2) take P = Re B for Re G and Q = Im B
+                    // for Im G; rows of Im Q take -Q for Re G and P for Im G
+                    // (the sign flip of packed FP16 is exact)
+                    const unsigned p0 = __shfl(pw0[g], src), p1 = __shfl(pw1[g], src);
+                    const unsigned q0 = __shfl(qw0[g], src), q1 = __shfl(qw1[g], src);
+                    const int d0 = __shfl(dw[g], src);
+                    const int a0 = min(max(4 * h - d0, -15), 4);   // a0 = 4h - d0, d0 the first tap
+                    const u32x4 sel = sel_tab[a0 + 15];
+                    const unsigned rh0 = kg < 2 ? p0 : q0 ^ 0x80008000u, rh1 = kg < 2 ? p1 : q1 ^ 0x80008000u;
+                    const unsigned ih0 = kg < 2 ? q0 : p0, ih1 = kg < 2 ? q1 : p1;
                     u32x4 vr, vi;
 #pragma unroll
                     for (int o = 0; o < 4; ++o) {
                         vr[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
                         vi[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
                     }
-                    const f16x8 br = __builtin_bit_cast(f16x8, vr), bi = __builtin_bit_cast(f16x8, vi);
+                                        const f16x8 br = __builtin_bit_cast(f16x8, vr), bi = __builtin_bit_cast(f16x8, vi);
+                    // every k_z tile's A fragment first, then the products:
+                    // one wait for the LDS reads instead of one per tile
+                    f16x8 va[KT];
 #pragma unroll
                     for (int t = 0; t < KT; ++t) {
-                        const unsigned char* p = ap + t * 16 * RB;
-                        const u32x2 h0 = *reinterpret_cast<const u32x2*>(p);
+                        const u32x2 h0 = *reinterpret_cast<const u32x2*>(ap + t * 16 * RB);
                         const u32x2 h1 = *reinterpret_cast<const u32x2*>(ap + dq[0] + t * 16 * RB);
-                        const f16x8 va = __builtin_bit_cast(f16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
-                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, br, accr[g][t], 0, 0, 0);
-                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va, bi, acci[g][t], 0, 0, 0);
+                        va[t] = __builtin_bit_cast(f16x8, u32x4{h0[0], h0[1], h1[0], h1[1]});
                     }
-                } else {
+#pragma unroll
+                    for (int t = 0; t < KT; ++t) {
+                        accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va[t], br, accr[g][t], 0, 0, 0);
+                        acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va[t], bi, acci[g][t], 0, 0, 0);
+                    }
+                                } else {
+                    // B operand: taps of this lane's pixel times the carrier,
+                    // placed at its 8 samples by byte permutes
+                    const float xn = __shfl(xw[g], src), crn = __shfl(crw[g], src), cin = __shfl(ciw[g], src);
+                    const float fl = floorf(xn);
+                    const float t = xn - fl;
+                    // a0 = 4h - d0 with d0 = floor(x) - 1 the first tap in the group window
+                    const int a0 = min(max(4 * h + 1 - static_cast<int>(fl), -15), 4);
+                    const u32x4 sel = sel_tab[a0 + 15];
+                    float w[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
+                    const float ca = kg < 2 ? crn : -cin;  // rows of Re Q: Re B (Re G), Im B (Im G)
+                    const float cb = kg < 2 ? cin : crn;   // rows of Im Q: -Im B, Re B
+                    const float r0 = w[0] * ca, r1 = w[1] * ca, r2 = w[2] * ca, r3 = w[3] * ca;
+                    const float i0 = w[0] * cb, i1 = w[1] * cb, i2 = w[2] * cb, i3 = w[3] * cb;
                     const unsigned rh0 = pack_bf16(r0, r1), rh1 = pack_bf16(r2, r3);
                     const unsigned ih0 = pack_bf16(i0, i1), ih1 = pack_bf16(i2, i3);
                     const unsigned rl0 = pack_lo(r0, r1, rh0), rl1 = pack_lo(r2, r3, rh1);
