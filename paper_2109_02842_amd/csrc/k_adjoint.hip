@@ -162,75 +162,80 @@ int launch_range_adjoint_wave(const HybridPlan& p, const float2* qt, char* ws, f
 // Adjoint of the back-projection (the transpose of A4):
 //   q~[c][kz][i] = sum_p sum_j [i = floor(u_c(p)) - 1 + j] w_j(p, c)
 //                  conj(exp(j k_ref l_c(p))) G~[p][kz].
-// Owner computes: one workgroup = one channel c x one block of KB k_z bins x
-// one segment of S range samples; every element of q~ is written once, by
+// Owner computes: one workgroup = one channel c x 64 k_z bins x one segment
+// [s0, s0 + S) of the range grid; every element of q~ is written once, by
 // one workgroup, with no atomics and no zero fill beforehand.  The
 // workgroup lists, in tile order, the 8x8 pixel tiles whose range interval
 // (lower bound: distance to the tile's rectangle; upper: its farthest
 // corner) can reach the segment; wavefront w takes list entries w, w+4, ...
-// Its lanes set up the tile's 64 pixels (first tap, four weights, carrier),
-// then the wavefront walks the pixels in order with the pixel's values
-// broadcast by readlane and its lanes over k_z bins (KB = 32: a lane per k_z
-// bin and real/imaginary part; KB = 64: a lane per bin, both parts), adding
-// each tap inside the segment into the wavefront's own LDS copy of the
-// segment (plain read-modify-write: a lane owns its address).  The four
-// copies are summed in a fixed order at the end, so the result is the same
-// bit for bit on every run.
+// For a tile, lane = pixel: its first tap relative to the segment, four
+// weights and carrier (one per plan block of k_z bins the workgroup
+// covers); the pixels whose taps reach the segment are ranked by first tap
+// (ties in lane order) and their records written to the wavefront's LDS in
+// that order.  Then lane = k_z bin: the wavefront walks the ranked pixels,
+// each record read by broadcast, and adds w_j conj(c) G~[p][kz] into four
+// complex accumulators for the samples cur .. cur + 3; once the next pixel's
+// first tap is past cur, the first of them goes into the lane's register
+// copy of the segment at cur and the window moves on.  A tile thus costs one
+// register-indexed update per sample it reaches, not four per pixel.  The
+// four wavefronts' copies are summed through LDS in a fixed order, so the
+// result is the same bit for bit on every run.
 struct AdjArgs {
-    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_seg, n_work, per_xcd;
+    int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_seg, n_work, per_xcd, block;
     double x0, y0, dx, dy, inv_du;
     float coef[4][4];
     double kref[kMaxBlocks];
 };
 
 constexpr int kAdjWaves = 4;
+constexpr int kAdjSeg = 32;    // range samples per workgroup
+constexpr int kAdjBins = 64;   // k_z bins per workgroup, one per lane
+
+struct AdjRec {                // one ranked pixel of a tile
+    float4 w;                  // tap weights
+    float4 car;                // carrier of bins [0, 32) (x, y) and [32, 64) (z, w) of the workgroup
+    int pix, i0, pad0, pad1;   // pixel index, first tap relative to the segment
+};
 
 __device__ __forceinline__ double rect_dist(double px, double py, double x0, double x1, double y0, double y1) {
     const double cx = fmin(fmax(px, x0), x1), cy = fmin(fmax(py, y0), y1);
     return sqrt((px - cx) * (px - cx) + (py - cy) * (py - cy));
 }
 
-template <int KB>
-constexpr int adj_segment() { return KB == 32 ? 32 : 16; }
-// floats of one wavefront's copy: [2 parts][KB rows][S + 1]
-template <int KB>
-constexpr int adj_copy_floats() { return 2 * KB * (adj_segment<KB>() + 1); }
-
-template <int KB>
 __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(const float2* __restrict__ Gt,
                                                                            const double* __restrict__ chan,
                                                                            const double* __restrict__ llo,
                                                                            AdjArgs a, float2* __restrict__ qt) {
-    constexpr int S = adj_segment<KB>();
-    constexpr int LR = S + 1;            // floats per row (odd: the rows of one column fall in distinct banks)
-    constexpr int PL = KB * LR;          // floats per part plane
-    constexpr int CF = adj_copy_floats<KB>();
-    constexpr int NT = 64 * kAdjWaves;
-    extern __shared__ float acc[];       // [kAdjWaves][2][KB][LR]
+    constexpr int S = kAdjSeg, NW = kAdjWaves, NT = 64 * NW;
     __shared__ int tiles[NT];
-    __shared__ int wcount[kAdjWaves];
+    __shared__ int wcount[NW];
+    __shared__ AdjRec rec[NW][64];
+    __shared__ float sum_re[S][65], sum_im[S][65];   // odd row length: a lane per bank
 
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
     if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
     const int c = work % a.n_ch;
     const int rest = work / a.n_ch;
     const int seg = rest % a.n_seg;
-    const int blk = rest / a.n_seg;
+    const int kb = rest / a.n_seg;
     const int s0 = seg * S;
+    const int kz0 = kb * kAdjBins;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double xT = chan[4 * c], yT = chan[4 * c + 1], xR = chan[4 * c + 2], yR = chan[4 * c + 3];
     const double l0 = llo[c];
-    const double kref_rev = a.kref[blk] * (0.5 / kPi);
-
-    for (int e = tid; e < kAdjWaves * CF; e += NT) acc[e] = 0.f;
-
-    // this lane's k_z bin and part(s)
-    const int kl = KB == 32 ? (lane & 31) : lane;
-    const int part = KB == 32 ? (lane >> 5) : 0;
-    const int kz = blk * KB + kl;
+    // the plan's reference wavenumbers of the workgroup's two halves of bins
+    const double kr0 = a.kref[kz0 / a.block] * (0.5 / kPi);
+    const double kr1 = a.kref[min(kz0 + 32, a.n_z - 1) / a.block] * (0.5 / kPi);
+    const int kz = kz0 + lane;
     const bool kok = kz < a.n_z;
-    float* mine = acc + wave * CF + part * PL + kl * LR;
+    AdjRec* myrec = rec[wave];
+
+    // the lane's copy of the segment, real and imaginary parts apart (each
+    // array stays in registers under a wavefront-uniform index)
+    float acr[S], aci[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) acr[i] = aci[i] = 0.f;
 
 #pragma unroll 1
     for (int t0 = 0; t0 < a.n_tiles; t0 += NT) {
@@ -259,124 +264,134 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
         if (lane == 0) wcount[wave] = __popcll(bal);
         __syncthreads();
         int base = 0, nl = 0;
-        for (int w = 0; w < kAdjWaves; ++w) {
+        for (int w = 0; w < NW; ++w) {
             base += w < wave ? wcount[w] : 0;
             nl += wcount[w];
         }
         if (hit) tiles[base + below] = t;
         __syncthreads();
 #pragma unroll 1
-        for (int k = wave; k < nl; k += kAdjWaves) {
+        for (int k = wave; k < nl; k += NW) {
             const int tt = tiles[k];
+            // lane = pixel of the tile
             const int px = (tt % a.tiles_x) * 8 + (lane & 7), py = (tt / a.tiles_x) * 8 + (lane >> 3);
-            // this lane's pixel: first tap relative to the segment, weights, conj carrier
-            int i0 = -1000000, pix = 0;
-            float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, cr = 0.f, ci = 0.f;
+            int i0 = 1 << 20;
+            AdjRec r{};
             if (px < a.nx && py < a.ny) {
                 const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
                 const double l = sqrt((xg - xT) * (xg - xT) + (yg - yT) * (yg - yT)) +
                                  sqrt((xg - xR) * (xg - xR) + (yg - yR) * (yg - yR));
                 const double u = (l - l0) * a.inv_du;
                 const double fl = floor(u);
-                const float tt2 = static_cast<float>(u - fl);
-                w0 = ((a.coef[0][3] * tt2 + a.coef[0][2]) * tt2 + a.coef[0][1]) * tt2 + a.coef[0][0];
-                w1 = ((a.coef[1][3] * tt2 + a.coef[1][2]) * tt2 + a.coef[1][1]) * tt2 + a.coef[1][0];
-                w2 = ((a.coef[2][3] * tt2 + a.coef[2][2]) * tt2 + a.coef[2][1]) * tt2 + a.coef[2][0];
-                w3 = ((a.coef[3][3] * tt2 + a.coef[3][2]) * tt2 + a.coef[3][1]) * tt2 + a.coef[3][0];
-                const float2 car = cis_rev(kref_rev * l);
-                cr = car.x;
-                ci = car.y;
+                const float tf = static_cast<float>(u - fl);
+                r.w.x = ((a.coef[0][3] * tf + a.coef[0][2]) * tf + a.coef[0][1]) * tf + a.coef[0][0];
+                r.w.y = ((a.coef[1][3] * tf + a.coef[1][2]) * tf + a.coef[1][1]) * tf + a.coef[1][0];
+                r.w.z = ((a.coef[2][3] * tf + a.coef[2][2]) * tf + a.coef[2][1]) * tf + a.coef[2][0];
+                r.w.w = ((a.coef[3][3] * tf + a.coef[3][2]) * tf + a.coef[3][1]) * tf + a.coef[3][0];
+                const float2 c0 = cis_rev(kr0 * l), c1 = cis_rev(kr1 * l);
+                r.car = make_float4(c0.x, c0.y, c1.x, c1.y);
                 i0 = static_cast<int>(fl) - 1 - s0;
-                pix = py * a.nx + px;
+                r.pix = py * a.nx + px;
+                r.i0 = i0;
             }
+            const bool valid = i0 >= -3 && i0 < S;
+            const unsigned long long vm = __ballot(valid);
+            const int n = __popcll(vm);
+            if (n == 0) continue;  // wavefront-uniform
+            // rank by first tap, ties in lane order: the smallest tap first,
+            // then one ballot per tap value up to the largest
+            int vmin = valid ? i0 : S;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) vmin = min(vmin, __shfl_xor(vmin, o));
+            vmin = __builtin_amdgcn_readfirstlane(vmin);
+            int rank = 0, placed = 0;
 #pragma unroll 1
-            for (int g0 = 0; g0 < 64; g0 += 16) {
-                // the group's G~ values first (one load per pixel and lane),
-                // so their latency is paid once per 16 pixels
-                float2 gv[16];
+            for (int v = vmin; placed < n; ++v) {
+                const unsigned long long m = __ballot(valid && i0 == v);
+                if (valid && i0 == v) rank = placed + __popcll(m & ((1ull << lane) - 1ull));
+                placed += __popcll(m);
+            }
+            if (valid) myrec[rank] = r;
+            wave_lds_sync();   // the records, written by their lanes, read by every lane below
+
+            // lane = k_z bin: walk the ranked pixels
+            float2 a0 = make_float2(0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
+            int cur = __builtin_amdgcn_readfirstlane(myrec[0].i0);
+#pragma unroll 1
+            for (int q0 = 0; q0 < n; q0 += 8) {
+                // the next eight pixels' G~ first, so their latency is paid once
+                float2 gv[8];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int ppix = __builtin_amdgcn_readlane(pix, g0 + q);  // 0 for pixels off the grid
-                    gv[q] = kok ? Gt[static_cast<size_t>(ppix) * a.n_z + kz] : make_float2(0.f, 0.f);
+                for (int qq = 0; qq < 8; ++qq) {
+                    const int q = min(q0 + qq, n - 1);
+                    const int pix = __builtin_amdgcn_readfirstlane(myrec[q].pix);
+                    gv[qq] = kok ? Gt[static_cast<size_t>(pix) * a.n_z + kz] : make_float2(0.f, 0.f);
                 }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int p = g0 + q;
-                    const int pi0 = __builtin_amdgcn_readlane(i0, p);
-                    if (pi0 < -3 || pi0 >= S) continue;  // wavefront-uniform
-                    const float pcr = rdl(cr, p), pci = rdl(ci, p);
-                    const float pw[4] = {rdl(w0, p), rdl(w1, p), rdl(w2, p), rdl(w3, p)};
-                    // conj(carrier) * G~
-                    const float hr = pcr * gv[q].x + pci * gv[q].y, hi = pcr * gv[q].y - pci * gv[q].x;
-                    const float h = part ? hi : hr;
-                    if (pi0 >= 0 && pi0 + 3 < S) {
-                        // all four taps in the segment: one batch of reads,
-                        // one wait, one batch of writes
-                        float* r = mine + pi0;
-                        if (KB == 32) {
-                            const float v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
-                            r[0] = v0 + pw[0] * h;
-                            r[1] = v1 + pw[1] * h;
-                            r[2] = v2 + pw[2] * h;
-                            r[3] = v3 + pw[3] * h;
-                        } else {
-                            const float v0 = r[0], v1 = r[1], v2 = r[2], v3 = r[3];
-                            const float u0 = r[PL], u1 = r[PL + 1], u2 = r[PL + 2], u3 = r[PL + 3];
-                            r[0] = v0 + pw[0] * hr;
-                            r[1] = v1 + pw[1] * hr;
-                            r[2] = v2 + pw[2] * hr;
-                            r[3] = v3 + pw[3] * hr;
-                            r[PL] = u0 + pw[0] * hi;
-                            r[PL + 1] = u1 + pw[1] * hi;
-                            r[PL + 2] = u2 + pw[2] * hi;
-                            r[PL + 3] = u3 + pw[3] * hi;
+                for (int qq = 0; qq < 8; ++qq) {
+                    if (q0 + qq >= n) break;  // wavefront-uniform
+                    const AdjRec& pr = myrec[q0 + qq];
+                    const int pi0 = __builtin_amdgcn_readfirstlane(pr.i0);
+                    while (cur < pi0) {  // samples before this pixel's first tap are complete
+                        if (cur >= 0 && cur < S) {
+                            acr[cur] += a0.x;
+                            aci[cur] += a0.y;
                         }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int i = pi0 + j;
-                            if (i >= 0 && i < S) {
-                                if (KB == 32) {
-                                    mine[i] += pw[j] * h;
-                                } else {
-                                    mine[i] += pw[j] * hr;
-                                    mine[PL + i] += pw[j] * hi;
-                                }
-                            }
-                        }
+                        a0 = a1;
+                        a1 = a2;
+                        a2 = a3;
+                        a3 = make_float2(0.f, 0.f);
+                        ++cur;
                     }
+                    const float4 w = pr.w, car = pr.car;
+                    const float cr = lane < 32 ? car.x : car.z, ci = lane < 32 ? car.y : car.w;
+                    // conj(carrier) * G~
+                    const float hr = cr * gv[qq].x + ci * gv[qq].y, hi = cr * gv[qq].y - ci * gv[qq].x;
+                    a0.x = fmaf(w.x, hr, a0.x);
+                    a0.y = fmaf(w.x, hi, a0.y);
+                    a1.x = fmaf(w.y, hr, a1.x);
+                    a1.y = fmaf(w.y, hi, a1.y);
+                    a2.x = fmaf(w.z, hr, a2.x);
+                    a2.y = fmaf(w.z, hi, a2.y);
+                    a3.x = fmaf(w.w, hr, a3.x);
+                    a3.y = fmaf(w.w, hi, a3.y);
                 }
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {   // the last pixel's four samples
+                if (cur >= 0 && cur < S) {
+                    acr[cur] += a0.x;
+                    aci[cur] += a0.y;
+                }
+                a0 = a1;
+                a1 = a2;
+                a2 = a3;
+                ++cur;
+            }
+            wave_lds_sync();   // every lane has read the records before the next tile's are written
         }
         __syncthreads();  // the tile list is rebuilt next
     }
-    const int n_s = min(S, a.n_l - s0);
-    float2* dst = qt + static_cast<size_t>(c) * a.n_z * a.n_l + s0;
-    for (int e = tid; e < KB * S; e += NT) {
-        const int r = e / S, i = e - r * S;
-        const int kzr = blk * KB + r;
-        if (kzr < a.n_z && i < n_s) {
-            float re = 0.f, im = 0.f;
-#pragma unroll
-            for (int w = 0; w < kAdjWaves; ++w) {
-                re += acc[w * CF + r * LR + i];
-                im += acc[w * CF + PL + r * LR + i];
-            }
-            dst[static_cast<size_t>(kzr) * a.n_l + i] = make_float2(re, im);
-        }
-    }
-}
 
-template <int KB>
-int launch_adjoint_cfg(const AdjArgs& a, unsigned blocks, hipStream_t s, const float2* Gt, const double* chan,
-                       const double* llo, float2* qt) {
-    auto fn = backproject_adjoint_kernel<KB>;
-    const size_t smem = static_cast<size_t>(kAdjWaves) * adj_copy_floats<KB>() * sizeof(float);
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
-    if (e != hipSuccess) return fail(PL_EDEVICE, "adjoint back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kAdjWaves), smem, s, Gt, chan, llo, a, qt);
-    return check_launch("adjoint back-projection");
+    // the wavefronts' copies, summed in wavefront order
+#pragma unroll 1
+    for (int w = 0; w < NW; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                sum_re[i][lane] = (w == 0 ? 0.f : sum_re[i][lane]) + acr[i];
+                sum_im[i][lane] = (w == 0 ? 0.f : sum_im[i][lane]) + aci[i];
+            }
+        }
+        __syncthreads();
+    }
+    const int n_s = min(S, a.n_l - s0);
+    for (int e = tid; e < kAdjBins * S; e += NT) {
+        const int r = e / S, i = e - r * S;
+        const int kzr = kz0 + r;
+        if (kzr < a.n_z && i < n_s)
+            qt[(static_cast<size_t>(c) * a.n_z + kzr) * a.n_l + s0 + i] = make_float2(sum_re[i][r], sum_im[i][r]);
+    }
 }
 
 }  // namespace
@@ -420,9 +435,10 @@ int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, cons
     a.ny = p.ny;
     a.tiles_x = (p.nx + 7) / 8;
     a.n_tiles = a.tiles_x * ((p.ny + 7) / 8);
-    const int S = p.block == 32 ? adj_segment<32>() : adj_segment<64>();
-    a.n_seg = (p.n_l + S - 1) / S;
-    const long long work = static_cast<long long>(p.n_ch) * p.n_blocks * a.n_seg;
+    a.n_seg = (p.n_l + kAdjSeg - 1) / kAdjSeg;
+    a.block = p.block;
+    const long long bins = (p.n_z + kAdjBins - 1) / kAdjBins;
+    const long long work = static_cast<long long>(p.n_ch) * bins * a.n_seg;
     if (work > (1LL << 30)) return fail(PL_EUNSUPPORTED, "adjoint back-projection: too many work items");
     a.n_work = static_cast<int>(work);
     a.per_xcd = (a.n_work + 7) / 8;
@@ -435,8 +451,8 @@ int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, cons
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
-    return p.block == 32 ? launch_adjoint_cfg<32>(a, blocks, s, Gt, dt.chan, llo, qt)
-                         : launch_adjoint_cfg<64>(a, blocks, s, Gt, dt.chan, llo, qt);
+    hipLaunchKernelGGL(backproject_adjoint_kernel, dim3(blocks), dim3(64 * kAdjWaves), 0, s, Gt, dt.chan, llo, a, qt);
+    return check_launch("adjoint back-projection");
 }
 
 }  // namespace pl

@@ -116,7 +116,7 @@ def test_adjoint_segment_lists_cover_every_tap(case, kz_block):
     if plan.bp_kernel != "pixel-lanes":
         pytest.skip("the adjoint runs on pixel-per-lane plans")
     gr, du, n_l = wl.grid, plan.du, plan.n_l
-    S = 32 if plan.block == 32 else 16
+    S = 32                               # range samples per adjoint workgroup
     n_seg = -(-n_l // S)
     tiles_x, tiles_y = -(-gr.nx // 8), -(-gr.ny // 8)
     X = gr.x0 + np.arange(gr.nx) * gr.dx
