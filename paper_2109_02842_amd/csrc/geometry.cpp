@@ -56,13 +56,19 @@ int plan_axis_fft(int n, AxisFft* out) {
     if (factor_radices(n, &f.rad)) {
         f.m = n;
     } else {
-        // any smooth m >= 2n - 1 serves; each radix stage is one pass through
-        // LDS with a barrier, so take the one with the least m x stages
-        // among those up to twice the smallest
+        // any smooth m >= 2n - 1 serves.  From n = 64 on, the smallest m =
+        // 64 R (R 2,3,5-smooth, at most 32): the wavefront chirp-z kernel's
+        // sizes.  Otherwise the workgroup kernel, each of whose radix stages
+        // is one pass through LDS with a barrier: the m with the least m x
+        // stages among those up to twice the smallest.
         int best = 0;
         long long best_cost = 0;
         Radices r;
-        for (int m = 2 * n - 1; m <= std::min(kMaxChirpLen, 2 * (2 * n - 1)); ++m) {
+        if (n >= 64)
+            for (int rr = (2 * n - 1 + 63) / 64; rr <= 32 && !best; ++rr)
+                if (is_fft_friendly(rr)) best = 64 * rr;
+        const bool wave = best != 0;
+        for (int m = 2 * n - 1; !wave && m <= std::min(kMaxChirpLen, 2 * (2 * n - 1)); ++m) {
             if (!factor_radices(m, &r)) continue;
             const long long cost = static_cast<long long>(m) * r.count;
             if (!best || cost < best_cost) {

@@ -314,6 +314,186 @@ __global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __r
     }
 }
 
+// Bluestein's chirp-z transform (as fft_chirp_strided_kernel) for a cyclic
+// length m = 64 R, one wavefront per transform and no workgroup barrier
+// inside a transform.  The forward product is formed through the inverse
+// wavefront FFT I (exponent +): DFT(a) = conj(I(conj a)).  I runs as in
+// wave_ifft up to its last radix-8 pass, which leaves butterfly (k1, m1) of
+// a lane holding Y[k1 + R (m1 + 8 m2)], m2 = 0..7, in registers; the product
+// Z = conj(Y) hat is taken there, and the convolution c = I(Z) comes from the
+// transpose of the same factorisation (the DFT matrix is symmetric): its
+// passes in reverse order take the scrambled index order in and give natural
+// order out, lane l holding c[64 a + l].  Transposed passes, with
+// n = 64 a + l, l = l1 + 8 l2, k = k1 + R (m1 + 8 m2):
+//   over m2 (in registers): sum Z w8^(l1 m2), stored at 9 m1 + l1 of row k1;
+//   over m1: twiddle w64^(l1 m1), sum w8^(l2 m1), stored at l of row k1;
+//   over k1 (lane l): twiddle wN^(l k1), R-point sum wR^(a k1).
+// A workgroup stages TB transforms of n points in LDS (loads and stores as
+// in fft_wave_strided_kernel); each wavefront has R rows of kWaveRow values
+// of its own for the passes.
+int set_lds_limit(const void* fn, size_t smem, const char* what);
+
+template <int R, int TB>
+__global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __restrict__ in, float2* __restrict__ out,
+                                                             const float2* __restrict__ tw,
+                                                             const float2* __restrict__ w,
+                                                             const float2* __restrict__ hat, FftArgs a) {
+    static_assert(R >= 2 && R <= 32, "cyclic lengths of 128 to 2048 points");
+    extern __shared__ float2 smem[];
+    const int PS = a.n | 1;                         // staged transform stride (odd)
+    float2* const stage = smem;                     // [TB][PS]
+    const int b0 = blockIdx.x * TB;
+    const int nb = min(TB, a.nbatch - b0);
+    const int tid = threadIdx.x;
+    const bool inv = a.sign > 0;
+    const int total = TB * a.n;
+    for (int e = tid; e < total; e += 256) {
+        int t, i;
+        if (a.n_fast_in) {
+            t = div_small(e, a.inv_n);
+            i = e - t * a.n;
+        } else {
+            i = e / TB;
+            t = e - i * TB;
+        }
+        if (t < nb) {
+            const int b = b0 + t;
+            const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
+            stage[t * PS + i] = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+        }
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    float2* const A = smem + ((TB * PS + 1) & ~1) + wave * R * kWaveRow;   // this wavefront's rows
+    for (int t = wave; t < nb; t += 4) {
+        float2* X = stage + t * PS;
+        // conj(x w), zero beyond n (x conjugated first for the inverse direction)
+        float2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int idx = 64 * j + lane;
+            float2 u = make_float2(0.f, 0.f);
+            if (idx < a.n) {
+                float2 x = X[idx];
+                if (inv) x.y = -x.y;
+                u = cmul(x, w[idx]);
+                u.y = -u.y;
+            }
+            v[j] = u;
+        }
+        // I: R-point transforms over a, twiddles wN^(l k1), rows k1
+        idft_reg<R>(v);
+#pragma unroll
+        for (int k1 = 1; k1 < R; ++k1) {
+            const float2 t1 = tw[lane * k1];
+            v[k1] = cmul(v[k1], make_float2(t1.x, -t1.y));
+        }
+        wave_lds_sync();   // the previous transform's last reads of the rows are done
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) A[k1 * kWaveRow + lane] = v[k1];
+        wave_lds_sync();
+        // I: first radix-8 pass over l2 (butterfly (k1, l1)), twiddles w64^(l1 m1)
+        for (int b = lane; b < 8 * R; b += 64) {
+            const int k1 = b >> 3, l1 = b & 7;
+            float2* row = A + k1 * kWaveRow;
+            float2 u[8];
+#pragma unroll
+            for (int l2 = 0; l2 < 8; ++l2) u[l2] = row[l1 + 8 * l2];
+            dft_small<8>(u, +1);
+#pragma unroll
+            for (int m1 = 1; m1 < 8; ++m1) {
+                const float2 t1 = tw[R * l1 * m1];
+                u[m1] = cmul(u[m1], make_float2(t1.x, -t1.y));
+            }
+#pragma unroll
+            for (int m1 = 0; m1 < 8; ++m1) row[9 * m1 + l1] = u[m1];
+        }
+        wave_lds_sync();
+        // I: second radix-8 pass over l1 (butterfly (k1, m1)) -> Y; Z = conj(Y) hat;
+        // transposed pass over m2 back into the same eight places
+        for (int b = lane; b < 8 * R; b += 64) {
+            const int k1 = b >> 3, m1 = b & 7;
+            float2* row = A + k1 * kWaveRow + 9 * m1;
+            float2 u[8];
+#pragma unroll
+            for (int l1 = 0; l1 < 8; ++l1) u[l1] = row[l1];
+            dft_small<8>(u, +1);
+#pragma unroll
+            for (int m2 = 0; m2 < 8; ++m2) u[m2] = cmul(make_float2(u[m2].x, -u[m2].y), hat[k1 + R * (m1 + 8 * m2)]);
+            dft_small<8>(u, +1);
+#pragma unroll
+            for (int l1 = 0; l1 < 8; ++l1) row[l1] = u[l1];
+        }
+        wave_lds_sync();
+        // transposed pass over m1 (butterfly (k1, l1)), twiddles w64^(l1 m1) first
+        for (int b = lane; b < 8 * R; b += 64) {
+            const int k1 = b >> 3, l1 = b & 7;
+            float2* row = A + k1 * kWaveRow;
+            float2 u[8];
+#pragma unroll
+            for (int m1 = 0; m1 < 8; ++m1) u[m1] = row[9 * m1 + l1];
+#pragma unroll
+            for (int m1 = 1; m1 < 8; ++m1) {
+                const float2 t1 = tw[R * l1 * m1];
+                u[m1] = cmul(u[m1], make_float2(t1.x, -t1.y));
+            }
+            dft_small<8>(u, +1);
+#pragma unroll
+            for (int l2 = 0; l2 < 8; ++l2) row[l1 + 8 * l2] = u[l2];
+        }
+        wave_lds_sync();
+        // transposed pass over k1 (lane l): twiddles wN^(l k1), R-point sums -> c[64 a + l]
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) v[k1] = A[k1 * kWaveRow + lane];
+#pragma unroll
+        for (int k1 = 1; k1 < R; ++k1) {
+            const float2 t1 = tw[lane * k1];
+            v[k1] = cmul(v[k1], make_float2(t1.x, -t1.y));
+        }
+        idft_reg<R>(v);
+        // X = w c for k < n (conjugated for the inverse direction), in place of the input
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int idx = 64 * j + lane;
+            if (idx < a.n) {
+                float2 y = cmul(v[j], w[idx]);
+                if (inv) y.y = -y.y;
+                X[idx] = y;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < total; e += 256) {
+        int t, i;
+        if (a.n_fast_out) {
+            t = div_small(e, a.inv_n);
+            i = e - t * a.n;
+        } else {
+            i = e / TB;
+            t = e - i * TB;
+        }
+        if (t < nb) {
+            const int b = b0 + t;
+            const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
+            out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(stage[t * PS + i], a.scale);
+        }
+    }
+}
+
+template <int R>
+int launch_chirp_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, const float2* w,
+                      const float2* hat, hipStream_t s, const char* what) {
+    constexpr int TB = 8;
+    const size_t smem = ((static_cast<size_t>(TB) * (a.n | 1) + 1) & ~1ull) * sizeof(float2) +
+                        4ull * R * kWaveRow * sizeof(float2);
+    auto fn = fft_chirp_wave_kernel<R, TB>;
+    int rc = set_lds_limit(reinterpret_cast<const void*>(fn), smem, what);
+    if (rc) return rc;
+    const long long blocks = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out, tw, w, hat, a);
+    return check_launch(what);
+}
+
 template <int R>
 int launch_fft_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, hipStream_t s,
                     const char* what) {
@@ -367,6 +547,20 @@ int run_fft(const float2* in, float2* out, const AxisFft& f, const char* tables,
     if (nbatch <= 0) return PL_OK;
     if (nbatch > (1LL << 31) - 1) return fail(PL_EUNSUPPORTED, "%s: too many transforms", what);
     const float2* tw = reinterpret_cast<const float2*>(tables + f.off_tw);
+    if (f.chirp && f.m % 64 == 0 && 2 * f.n <= f.m && nbatch + inner < (1LL << 21)) {
+        // the wavefront chirp-z kernel (float-reciprocal index splits: exact
+        // below 2^21 with its TB * n element loop)
+        const float2* w = reinterpret_cast<const float2*>(tables + f.off_chirp);
+        const float2* hat = reinterpret_cast<const float2*>(tables + f.off_hat);
+        switch (f.m / 64) {
+#define PL_CW(R) \
+            case R: return launch_chirp_wave<R>(a, in, out, tw, w, hat, s, what);
+            PL_CW(2) PL_CW(3) PL_CW(4) PL_CW(5) PL_CW(6) PL_CW(8) PL_CW(9) PL_CW(10) PL_CW(12) PL_CW(15) PL_CW(16)
+            PL_CW(18) PL_CW(20) PL_CW(24) PL_CW(25) PL_CW(27) PL_CW(30) PL_CW(32)
+#undef PL_CW
+            default: break;
+        }
+    }
     if (f.chirp) {
         // the chirp kernel splits indices with float reciprocals (div_small):
         // exact while index + divisor < 2^22

@@ -137,12 +137,12 @@ def _smooth(n):
     return n == 1
 
 
-@pytest.mark.parametrize("n_scan", [7, 131, 509, 2304, 2310, 4096, 4093])
+@pytest.mark.parametrize("n_scan", [7, 37, 131, 226, 389, 509, 1000, 1100, 2304, 2310, 4096, 4093])
 def test_plan_blocks_and_transform_length_at_any_scan_length(n_scan):
     # Every k_z block gets its band-centre reference wavenumber, also past
     # 64 blocks (scans longer than 2048 with 32-bin blocks), and the scan
     # transform runs through n_scan itself when it is 2,3,5-smooth, else
-    # through the smallest smooth length >= 2 n_scan - 1 (chirp-z).
+    # through a smooth chirp-z length >= 2 n_scan - 1.
     a = replace(W.C1.array, n_scan=n_scan)
     g = pr.make_geometry(a)
     for opts in ({}, dict(kz_per_lane=1)):
@@ -155,11 +155,18 @@ def test_plan_blocks_and_transform_length_at_any_scan_length(n_scan):
             kr = np.sqrt(kr2[kr2 > 0])
             want = 0.5 * (kr.min() + kr.max()) if kr.size else 0.0
             assert math.isclose(p.k_ref[b], want, rel_tol=1e-12, abs_tol=1e-9)
-        # smooth lengths run as they are; any other through the chirp-z
-        # length >= 2n - 1 (up to twice that) with the fewest length x stages
+        # smooth lengths run as they are; any other through a chirp-z length
+        # m >= 2n - 1: from n = 64 on the smallest m = 64 R with R smooth and
+        # at most 32 (the wavefront kernel), else the m up to twice the
+        # smallest with the fewest length x stages
         lo = 2 * n_scan - 1
-        want_len = n_scan if _smooth(n_scan) else min((m for m in range(lo, 2 * lo + 1) if _smooth(m)),
-                                                       key=lambda m: (m * _stages(m), m))
+        wave = [64 * r for r in range(2, 33) if _smooth(r) and 64 * r >= lo] if n_scan >= 64 else []
+        if _smooth(n_scan):
+            want_len = n_scan
+        elif wave:
+            want_len = wave[0]
+        else:
+            want_len = min((m for m in range(lo, 2 * lo + 1) if _smooth(m)), key=lambda m: (m * _stages(m), m))
         assert p.scan_fft_len == want_len
     assert pr.fft_workspace_bytes(g) >= 8 * want_len * (1 if _smooth(n_scan) else 3)
     assert _smooth(want_len) and want_len >= (n_scan if _smooth(n_scan) else 2 * n_scan - 1)
