@@ -329,8 +329,9 @@ __global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __r
 //   over m1: twiddle w64^(l1 m1), sum w8^(l2 m1), stored at l of row k1;
 //   over k1 (lane l): twiddle wN^(l k1), R-point sum wR^(a k1).
 // A workgroup stages TB transforms of n points in LDS (loads and stores as
-// in fft_wave_strided_kernel); each wavefront has R rows of kWaveRow values
-// of its own for the passes.
+// in fft_wave_strided_kernel) beside the twiddles, the chirp and the filter
+// (read once per workgroup); each wavefront has R rows of kWaveRow values of
+// its own for the passes.
 int set_lds_limit(const void* fn, size_t smem, const char* what);
 
 template <int R, int TB>
@@ -339,32 +340,73 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
                                                              const float2* __restrict__ w,
                                                              const float2* __restrict__ hat, FftArgs a) {
     static_assert(R >= 2 && R <= 32, "cyclic lengths of 128 to 2048 points");
+    constexpr int N = 64 * R;
     extern __shared__ float2 smem[];
     const int PS = a.n | 1;                         // staged transform stride (odd)
     float2* const stage = smem;                     // [TB][PS]
-    const int b0 = blockIdx.x * TB;
-    const int nb = min(TB, a.nbatch - b0);
+    float2* const ltw = smem + ((TB * PS + 1) & ~1);   // twiddles [N], filter [N], chirp [n]
+    float2* const lhat = ltw + N;
+    float2* const lw = lhat + N;
     const int tid = threadIdx.x;
     const bool inv = a.sign > 0;
     const int total = TB * a.n;
-    for (int e = tid; e < total; e += 256) {
-        int t, i;
-        if (a.n_fast_in) {
-            t = div_small(e, a.inv_n);
-            i = e - t * a.n;
-        } else {
-            i = e / TB;
-            t = e - i * TB;
+    for (int e = tid; e < N; e += 256) {
+        ltw[e] = tw[e];
+        lhat[e] = hat[e];
+    }
+    for (int e = tid; e < a.n; e += 256) lw[e] = w[e];
+    // The workgroup takes groups of TB transforms in turn (the tables above
+    // are read once per workgroup); the next group's input is loaded into
+    // registers while the current one is transformed.
+    constexpr int KPT = (TB * 1024 + 255) / 256;   // staged values per thread (n <= 1024)
+    const int n_groups = (a.nbatch + TB - 1) / TB;
+    float2 pre[KPT];
+    auto fetch = [&](int g) {
+        const int gb0 = g * TB, gnb = min(TB, a.nbatch - gb0);
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int e = tid + 256 * j;
+            pre[j] = make_float2(0.f, 0.f);
+            if (e < total) {
+                int t, i;
+                if (a.n_fast_in) {
+                    t = div_small(e, a.inv_n);
+                    i = e - t * a.n;
+                } else {
+                    i = e / TB;
+                    t = e - i * TB;
+                }
+                if (t < gnb) {
+                    const int b = gb0 + t;
+                    const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
+                    pre[j] = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+                }
+            }
         }
-        if (t < nb) {
-            const int b = b0 + t;
-            const int o = div_small(b, a.inv_inner), s = b - o * a.inner;
-            stage[t * PS + i] = in[o * a.in_so + s * a.in_si + i * a.in_sn];
+    };
+    if (blockIdx.x < n_groups) fetch(blockIdx.x);
+    for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int b0 = grp * TB;
+    const int nb = min(TB, a.nbatch - b0);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int e = tid + 256 * j;
+        if (e < total) {
+            int t, i;
+            if (a.n_fast_in) {
+                t = div_small(e, a.inv_n);
+                i = e - t * a.n;
+            } else {
+                i = e / TB;
+                t = e - i * TB;
+            }
+            stage[t * PS + i] = pre[j];
         }
     }
     __syncthreads();
+    if (grp + static_cast<int>(gridDim.x) < n_groups) fetch(grp + gridDim.x);
     const int wave = tid >> 6, lane = tid & 63;
-    float2* const A = smem + ((TB * PS + 1) & ~1) + wave * R * kWaveRow;   // this wavefront's rows
+    float2* const A = lw + ((a.n + 1) & ~1) + wave * R * kWaveRow;   // this wavefront's rows
     for (int t = wave; t < nb; t += 4) {
         float2* X = stage + t * PS;
         // conj(x w), zero beyond n (x conjugated first for the inverse direction)
@@ -376,7 +418,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
             if (idx < a.n) {
                 float2 x = X[idx];
                 if (inv) x.y = -x.y;
-                u = cmul(x, w[idx]);
+                u = cmul(x, lw[idx]);
                 u.y = -u.y;
             }
             v[j] = u;
@@ -385,7 +427,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
         idft_reg<R>(v);
 #pragma unroll
         for (int k1 = 1; k1 < R; ++k1) {
-            const float2 t1 = tw[lane * k1];
+            const float2 t1 = ltw[lane * k1];
             v[k1] = cmul(v[k1], make_float2(t1.x, -t1.y));
         }
         wave_lds_sync();   // the previous transform's last reads of the rows are done
@@ -402,7 +444,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
             dft_small<8>(u, +1);
 #pragma unroll
             for (int m1 = 1; m1 < 8; ++m1) {
-                const float2 t1 = tw[R * l1 * m1];
+                const float2 t1 = ltw[R * l1 * m1];
                 u[m1] = cmul(u[m1], make_float2(t1.x, -t1.y));
             }
 #pragma unroll
@@ -419,7 +461,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
             for (int l1 = 0; l1 < 8; ++l1) u[l1] = row[l1];
             dft_small<8>(u, +1);
 #pragma unroll
-            for (int m2 = 0; m2 < 8; ++m2) u[m2] = cmul(make_float2(u[m2].x, -u[m2].y), hat[k1 + R * (m1 + 8 * m2)]);
+            for (int m2 = 0; m2 < 8; ++m2) u[m2] = cmul(make_float2(u[m2].x, -u[m2].y), lhat[k1 + R * (m1 + 8 * m2)]);
             dft_small<8>(u, +1);
 #pragma unroll
             for (int l1 = 0; l1 < 8; ++l1) row[l1] = u[l1];
@@ -434,7 +476,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
             for (int m1 = 0; m1 < 8; ++m1) u[m1] = row[9 * m1 + l1];
 #pragma unroll
             for (int m1 = 1; m1 < 8; ++m1) {
-                const float2 t1 = tw[R * l1 * m1];
+                const float2 t1 = ltw[R * l1 * m1];
                 u[m1] = cmul(u[m1], make_float2(t1.x, -t1.y));
             }
             dft_small<8>(u, +1);
@@ -447,7 +489,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
         for (int k1 = 0; k1 < R; ++k1) v[k1] = A[k1 * kWaveRow + lane];
 #pragma unroll
         for (int k1 = 1; k1 < R; ++k1) {
-            const float2 t1 = tw[lane * k1];
+            const float2 t1 = ltw[lane * k1];
             v[k1] = cmul(v[k1], make_float2(t1.x, -t1.y));
         }
         idft_reg<R>(v);
@@ -456,7 +498,7 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
         for (int j = 0; j < R; ++j) {
             const int idx = 64 * j + lane;
             if (idx < a.n) {
-                float2 y = cmul(v[j], w[idx]);
+                float2 y = cmul(v[j], lw[idx]);
                 if (inv) y.y = -y.y;
                 X[idx] = y;
             }
@@ -478,18 +520,28 @@ __global__ __launch_bounds__(256) void fft_chirp_wave_kernel(const float2* __res
             out[o * a.out_so + s * a.out_si + i * a.out_sn] = cscale(stage[t * PS + i], a.scale);
         }
     }
+    __syncthreads();   // the staged transforms are stored before the next group is staged
+    }
 }
 
 template <int R>
 int launch_chirp_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, const float2* w,
                       const float2* hat, hipStream_t s, const char* what) {
-    constexpr int TB = 8;
-    const size_t smem = ((static_cast<size_t>(TB) * (a.n | 1) + 1) & ~1ull) * sizeof(float2) +
-                        4ull * R * kWaveRow * sizeof(float2);
+    constexpr int TB = 4;   // one transform per wavefront: two workgroups per CU up to R = 16
+    const size_t smem = (((static_cast<size_t>(TB) * (a.n | 1) + 1) & ~1ull) + 2ull * 64 * R +
+                         ((static_cast<size_t>(a.n) + 1) & ~1ull) + 4ull * R * kWaveRow) * sizeof(float2);
     auto fn = fft_chirp_wave_kernel<R, TB>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), smem, what);
     if (rc) return rc;
-    const long long blocks = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
+    // as many workgroups as are resident at once (LDS-bound), each taking
+    // groups of transforms in turn
+    const long long groups = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus < 1)
+        return fail(PL_EDEVICE, "%s: compute-unit count unavailable", what);
+    const long long per_cu = std::max<long long>(1, std::min<long long>(8, kMaxLds / smem));
+    const long long blocks = std::min(groups, per_cu * cus);
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out, tw, w, hat, a);
     return check_launch(what);
 }
