@@ -484,8 +484,9 @@ def main() -> int:
 def bench_batch(args, torch, pr, W) -> int:
     """The uneven batch (16 monostatic scans of different chords, elements,
     scan lengths and frequency counts, 128 x 128 images): one
-    reconstruct_hybrid_batch call captured in a graph and replayed; the
-    same scans as 16 separate reconstruct_hybrid calls for comparison."""
+    reconstruct_hybrid_batch call (plan tables prepared once) captured in a
+    graph and replayed; the same scans as 16 separate reconstruct_hybrid
+    calls, plain and prepared, for comparison."""
     wls = W.batch_c5()
     geoms = [pr.make_geometry(w.array) for w in wls]
     echoes = []
@@ -528,7 +529,18 @@ def bench_batch(args, torch, pr, W) -> int:
             pr.reconstruct_hybrid(g, w.grid, e, out=o, ws=ws, **so)
 
     ms_single = timed(singles, args.steps, 1)
-    log(f"[bench] C5: graph replay {ms:.3f} ms, batch call {ms_call:.3f} ms, 16 separate calls {ms_single:.3f} ms")
+    # the same with each scan's tables prepared once (the graph replays the
+    # prepared batch call)
+    for g, w, ws, so in zip(geoms, wls, wss, batch.opts):
+        pr.hybrid_prepare(g, w.grid, ws=ws, **so)
+
+    def singles_prepared():
+        for g, w, e, o, ws, so in zip(geoms, wls, echoes, outs, wss, batch.opts):
+            pr.reconstruct_hybrid(g, w.grid, e, out=o, ws=ws, prepared=True, **so)
+
+    ms_single_p = timed(singles_prepared, args.steps, 1)
+    log(f"[bench] C5: graph replay {ms:.3f} ms (prepared batch), batch call {ms_call:.3f} ms, 16 separate calls "
+        f"{ms_single:.3f} ms ({ms_single_p:.3f} ms prepared)")
     achieved = FLOP_PER_TERM * terms / (ms * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": voxels / (ms * 1e-3), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
@@ -543,7 +555,8 @@ def bench_batch(args, torch, pr, W) -> int:
                      "flop_per_launch": FLOP_PER_TERM * terms, "avg_launch_ms": ms},
         "batch": {"scans": len(wls), "queued_scans": batch.queued_scans, "work_items": batch.work_items,
                   "workgroups": batch.workgroups, "ms_graph_replay": ms, "ms_batch_call": ms_call,
-                  "ms_separate_calls": ms_single, "autotune_s": tune_s,
+                  "ms_separate_calls": ms_single, "ms_separate_calls_prepared": ms_single_p,
+                  "autotune_s": tune_s,
                   "scan_lengths": [w.array.n_scan for w in wls],
                   "tuned_options": [{k: v for k, v in o.items() if k != "precision"} for o in batch.opts]},
     }

@@ -500,6 +500,12 @@ int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spe
  * graph; calls on one batch, or sharing one workspace, must not overlap.
  * hybrid_batch_info: workspace bytes, scans in the persistent launch, its
  * work items and workgroups (any pointer may be NULL).
+ * hybrid_batch_prepare writes every scan's plan tables (wavenumber tables,
+ * tile geometry, transform tables) into the workspace on `stream`;
+ * reconstruct_hybrid_batch_prepared is reconstruct_hybrid_batch without
+ * those steps, for a workspace prepared for this batch on this device and
+ * not written since by anything else (the plan-caching form of the batch,
+ * as hybrid_prepare / reconstruct_hybrid_prepared are for one scan).
  * Errors: PL_EINVAL, PL_EUNSUPPORTED, PL_EWORKSPACE, PL_EDEVICE.
  */
 typedef struct pl_hybrid_batch pl_hybrid_batch; /* opaque */
@@ -510,6 +516,9 @@ int hybrid_batch_info(const pl_hybrid_batch* batch, size_t* workspace_bytes, int
                       int32_t* work_items, int32_t* workgroups);
 int reconstruct_hybrid_batch(const pl_hybrid_batch* batch, const float* const* echoes_dev,
                              float* const* images_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+int hybrid_batch_prepare(const pl_hybrid_batch* batch, void* ws, size_t ws_bytes, hipStream_t stream);
+int reconstruct_hybrid_batch_prepared(const pl_hybrid_batch* batch, const float* const* echoes_dev,
+                                      float* const* images_dev, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------- back-projection */
 /*

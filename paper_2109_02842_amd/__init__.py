@@ -111,6 +111,8 @@ _SIGNATURES = {
     "hybrid_batch_info": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
     "reconstruct_hybrid_batch": (C.c_int, [_P, _P, _P, _P, C.c_size_t, _P]),
+    "hybrid_batch_prepare": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "reconstruct_hybrid_batch_prepared": (C.c_int, [_P, _P, _P, _P, C.c_size_t, _P]),
     "last_error": (C.c_char_p, []),
 }
 EXPORTED = tuple(_SIGNATURES)
@@ -459,26 +461,40 @@ class HybridBatch:
             pass
 
 
-def reconstruct_hybrid_batch(batch: HybridBatch, echoes, outs=None, ws=None):
-    """Images of every scan of ``batch`` (list of complex64 device tensors)."""
+def hybrid_batch_prepare(batch: HybridBatch, ws):
+    """Write every scan's plan tables into ``ws`` (for
+    ``reconstruct_hybrid_batch(..., prepared=True)`` with the same ``ws``)."""
+    ws = _ws(ws, batch.workspace_bytes)
+    _check(lib().hybrid_batch_prepare(batch.handle, C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return ws
+
+
+def reconstruct_hybrid_batch(batch: HybridBatch, echoes, outs=None, ws=None, prepared: bool = False):
+    """Images of every scan of ``batch`` (list of complex64 device tensors).
+    ``prepared``: ``ws`` holds the plan tables (hybrid_batch_prepare)."""
     torch = _torch()
     n = len(batch)
     if len(echoes) != n:
         raise ValueError(f"{n} echoes expected")
+    if prepared and ws is None:
+        raise ValueError("a prepared call needs the prepared workspace")
     ws = _ws(ws, batch.workspace_bytes)
     if outs is None:
         outs = [torch.empty(batch.image_shape(i), dtype=torch.complex64, device=echoes[i].device) for i in range(n)]
     e_ptrs = (_P * n)(*[_dev_c64(echoes[i], batch.geoms[i].echo_shape, f"echo {i}") for i in range(n)])
     o_ptrs = (_P * n)(*[_dev_c64(outs[i], batch.image_shape(i), f"out {i}") for i in range(n)])
-    _check(lib().reconstruct_hybrid_batch(batch.handle, C.cast(e_ptrs, _P), C.cast(o_ptrs, _P),
-                                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    fn = lib().reconstruct_hybrid_batch_prepared if prepared else lib().reconstruct_hybrid_batch
+    _check(fn(batch.handle, C.cast(e_ptrs, _P), C.cast(o_ptrs, _P), C.c_void_p(ws.data_ptr()), ws.numel(),
+              _stream()))
     return outs
 
 
 class CapturedBatch:
     """A batch call captured once in a graph (torch.cuda.CUDAGraph) and
     replayed: the echo and image tensors and the workspace are fixed at
-    capture; copy new echoes into ``echoes`` before ``replay()``."""
+    capture; copy new echoes into ``echoes`` before ``replay()``.  The
+    workspace is prepared once (plan tables) and the graph holds the
+    prepared call, so a replay runs no table kernels."""
 
     def __init__(self, batch: HybridBatch, echoes):
         torch = _torch()
@@ -487,12 +503,13 @@ class CapturedBatch:
         self.ws = workspace(batch.workspace_bytes)
         self.outs = [torch.empty(batch.image_shape(i), dtype=torch.complex64, device="cuda")
                      for i in range(len(batch))]
-        # one eager call first (lazily created device tables, kernel attributes)
-        reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws)
+        # the tables, then one eager call (kernel attributes set on first use)
+        hybrid_batch_prepare(batch, self.ws)
+        reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws, prepared=True)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws)
+            reconstruct_hybrid_batch(batch, self.echoes, self.outs, self.ws, prepared=True)
 
     def replay(self):
         self.graph.replay()

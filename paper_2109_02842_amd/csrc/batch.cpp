@@ -195,22 +195,34 @@ int hybrid_batch_info(const pl_hybrid_batch* b, size_t* workspace_bytes, int32_t
     return PL_OK;
 }
 
-int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoes, float* const* images, void* ws,
-                             size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the batch calls: the workspace and the device.
+int check_batch_ws(const pl_hybrid_batch* b, void* ws, size_t ws_bytes, const char* what) {
     using namespace pl;
-    clear_error();
-    if (!b || !echoes || !images) return fail(PL_EINVAL, "reconstruct_hybrid_batch: null argument");
-    const int n = static_cast<int>(b->plans.size());
-    for (int s = 0; s < n; ++s)
-        if (!echoes[s] || !images[s]) return fail(PL_EINVAL, "reconstruct_hybrid_batch: scan %d has a null buffer", s);
-    if (!ws) return fail(PL_EWORKSPACE, "reconstruct_hybrid_batch: null workspace");
-    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
-        return fail(PL_EWORKSPACE, "reconstruct_hybrid_batch: workspace must be 256-byte aligned");
-    if (ws_bytes < b->total)
-        return fail(PL_EWORKSPACE, "reconstruct_hybrid_batch: workspace of %zu bytes, %zu needed", ws_bytes, b->total);
+    if (!ws) return fail(PL_EWORKSPACE, "%s: null workspace", what);
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(PL_EWORKSPACE, "%s: workspace must be 256-byte aligned", what);
+    if (ws_bytes < b->total) return fail(PL_EWORKSPACE, "%s: workspace of %zu bytes, %zu needed", what, ws_bytes, b->total);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
-        return fail(PL_EDEVICE, "reconstruct_hybrid_batch: the batch was made on device %d", b->device);
+        return fail(PL_EDEVICE, "%s: the batch was made on device %d", what, b->device);
+    return PL_OK;
+}
+
+// The batch call; with `tables` false the workspace already holds every
+// scan's plan tables (hybrid_batch_prepare).
+int batch_impl(const pl_hybrid_batch* b, const float* const* echoes, float* const* images, void* ws, size_t ws_bytes,
+               hipStream_t stream, bool tables, const char* what) {
+    using namespace pl;
+    clear_error();
+    if (!b || !echoes || !images) return fail(PL_EINVAL, "%s: null argument", what);
+    const int n = static_cast<int>(b->plans.size());
+    for (int s = 0; s < n; ++s)
+        if (!echoes[s] || !images[s]) return fail(PL_EINVAL, "%s: scan %d has a null buffer", what, s);
+    int rc0 = check_batch_ws(b, ws, ws_bytes, what);
+    if (rc0) return rc0;
     char* w = static_cast<char*>(ws);
     std::vector<DeviceTables> dts(n);
     int rc = PL_OK;
@@ -241,7 +253,7 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoe
         hipStream_t hs = b->helpers[s % b->n_helpers];
         char* ws_s = w + b->ws_off[s];
         float2* spec = reinterpret_cast<float2*>(ws_s + p.off_spec);
-        if ((rc = launch_plan_tables(p, dts[s], ws_s, hs))) return rc;
+        if (tables && (rc = launch_plan_tables(p, dts[s], ws_s, hs))) return rc;
         if ((rc = launch_scan_fft(b->geoms[s], reinterpret_cast<const float2*>(echoes[s]), spec, p.zfft,
                                   ws_s + p.off_zfft, hs)))
             return rc;
@@ -283,6 +295,35 @@ int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoe
             return rc;
     }
     if ((rc = join())) return rc;
+    return PL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int reconstruct_hybrid_batch(const pl_hybrid_batch* b, const float* const* echoes, float* const* images, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    return batch_impl(b, echoes, images, ws, ws_bytes, stream, true, "reconstruct_hybrid_batch");
+}
+
+int reconstruct_hybrid_batch_prepared(const pl_hybrid_batch* b, const float* const* echoes, float* const* images,
+                                      void* ws, size_t ws_bytes, hipStream_t stream) {
+    return batch_impl(b, echoes, images, ws, ws_bytes, stream, false, "reconstruct_hybrid_batch_prepared");
+}
+
+int hybrid_batch_prepare(const pl_hybrid_batch* b, void* ws, size_t ws_bytes, hipStream_t stream) {
+    using namespace pl;
+    clear_error();
+    if (!b) return fail(PL_EINVAL, "hybrid_batch_prepare: null batch");
+    int rc = check_batch_ws(b, ws, ws_bytes, "hybrid_batch_prepare");
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    for (size_t s = 0; s < b->plans.size(); ++s) {
+        DeviceTables dt;
+        if ((rc = b->geoms[s]->device_tables(&dt, stream))) return rc;
+        if ((rc = launch_plan_tables(b->plans[s], dt, w + b->ws_off[s], stream))) return rc;
+    }
     return PL_OK;
 }
 

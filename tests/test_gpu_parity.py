@@ -688,6 +688,24 @@ def test_batch_graph_replays():
         del junk
 
 
+def test_prepared_batch_matches_plain_call():
+    # the plan-caching form: tables written once by hybrid_batch_prepare,
+    # then calls without them give the plain call's images bit for bit
+    scans = _small_batch()
+    geoms = [pr.make_geometry(a) for a, _, _ in scans]
+    batch = pr.HybridBatch(geoms, [g for _, g, _ in scans])
+    echoes = [dev(W.random_echo(a, 300 + i)) for i, (a, _, _) in enumerate(scans)]
+    plain = [host(t) for t in pr.reconstruct_hybrid_batch(batch, echoes)]
+    ws = pr.workspace(batch.workspace_bytes)
+    pr.hybrid_batch_prepare(batch, ws)
+    for _ in range(2):
+        got = [host(t) for t in pr.reconstruct_hybrid_batch(batch, echoes, ws=ws, prepared=True)]
+        for i in range(len(scans)):
+            assert rel(got[i], plain[i]) == 0.0, i
+    with pytest.raises(ValueError):
+        pr.reconstruct_hybrid_batch(batch, echoes, prepared=True)
+
+
 def test_autotuned_batch_matches_single_scans(tmp_path):
     # per-scan tuned launch shapes (timed on the device, cached): the batch
     # call equals single-scan calls with the same options bit for bit and
