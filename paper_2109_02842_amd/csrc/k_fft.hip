@@ -252,6 +252,19 @@ __global__ __launch_bounds__(256) void fft_chirp_strided_kernel(const float2* __
     }
 }
 
+// Workgroups of 256 threads of `fn` with `smem` bytes of LDS that are
+// resident at once on the device, at most `groups`: the grid of a launch
+// whose workgroups loop over groups of work.  Returns the count, or minus an
+// error code.
+int resident_grid(const void* fn, size_t smem, const char* what, long long groups) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, smem) != hipSuccess)
+        return -fail(PL_EDEVICE, "%s: occupancy query failed", what);
+    return static_cast<int>(std::max<long long>(1, std::min<long long>(groups, static_cast<long long>(std::max(1, per_cu)) * cus)));
+}
+
 // The same batched strided FFT for N = 64 R (R at most 8) on the wavefront
 // FFT (wave_ifft): a workgroup stages TB transforms in LDS with loads and
 // stores that run along whichever of (transform, element) is contiguous in
@@ -533,16 +546,12 @@ int launch_chirp_wave(const FftArgs& a, const float2* in, float2* out, const flo
     auto fn = fft_chirp_wave_kernel<R, TB>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), smem, what);
     if (rc) return rc;
-    // as many workgroups as are resident at once (LDS-bound), each taking
-    // groups of transforms in turn
+    // as many workgroups as are resident at once, each taking groups of
+    // transforms in turn
     const long long groups = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                 hipSuccess || cus < 1)
-        return fail(PL_EDEVICE, "%s: compute-unit count unavailable", what);
-    const long long per_cu = std::max<long long>(1, std::min<long long>(8, kMaxLds / smem));
-    const long long blocks = std::min(groups, per_cu * cus);
-    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out, tw, w, hat, a);
+    rc = resident_grid(reinterpret_cast<const void*>(fn), smem, what, groups);
+    if (rc <= 0) return -rc;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(rc)), dim3(256), smem, s, in, out, tw, w, hat, a);
     return check_launch(what);
 }
 
