@@ -268,7 +268,7 @@ int resident_grid(const void* fn, size_t smem, const char* what, long long group
 // The same batched strided FFT for N = 64 R (R at most 8) on the wavefront
 // FFT (wave_ifft): a workgroup stages TB transforms in LDS with loads and
 // stores that run along whichever of (transform, element) is contiguous in
-// memory (TB = 16: 128-byte runs across transforms), its four wavefronts
+// memory (TB = 8: 64-byte runs across transforms), its four wavefronts
 // transform them in place (wave_ifft's last radix-8 pass is a single pass
 // for R <= 8, so every lane has read its inputs before any output lands),
 // and the forward direction conjugates on the way in and out.  Transforms
@@ -558,7 +558,10 @@ int launch_chirp_wave(const FftArgs& a, const float2* in, float2* out, const flo
 template <int R>
 int launch_fft_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, hipStream_t s,
                     const char* what) {
-    constexpr int TB = 16;
+    // eight transforms per workgroup: 64-byte runs on the strided side and
+    // eight resident workgroups per CU at R = 4 (sixteen transforms, with
+    // 128-byte runs but half the workgroups, ran 15-20 % slower)
+    constexpr int TB = 8;
     const size_t smem = static_cast<size_t>(TB) * (kWaveRow * R + 2) * sizeof(float2);
     auto fn = fft_wave_strided_kernel<R, TB>;
     if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
