@@ -293,14 +293,18 @@ struct BatchScanDesc {
     unsigned long long q_off, tab_off, g_off;
 };
 
-#if defined(__HIP_DEVICE_COMPILE__)
-#define PL_DMA16(SRC, DST) __builtin_amdgcn_global_load_lds((SRC), (DST), 16, 0, 0)
-#else
-#define PL_DMA16(SRC, DST) ((void)(SRC), (void)(DST))  // device-only builtin (host pass emits stubs)
-#endif
-
 constexpr int kGatherWaves = 4;   // wavefronts per workgroup
 constexpr int kGatherBatch = 4;   // channels per weight batch
+
+typedef __attribute__((address_space(3))) unsigned char* lds_bytes_t;
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) GatherTileEntry* const_tile_t;
+#define PL_LDS_COPY16(RS, DST, VOFF) __builtin_amdgcn_raw_ptr_buffer_load_lds((RS), (DST), 16, (VOFF), 0, 0, 0)
+#else
+// host pass: parsed only, never run (the builtin is device-only)
+typedef const GatherTileEntry* const_tile_t;
+#define PL_LDS_COPY16(RS, DST, VOFF) ((void)(RS), (void)(DST), (void)(VOFF))
+#endif
 
 // RSC 16-byte chunks per LDS row, of which nchk (the window) are staged.
 // With A, B = (l_c -+ reach - l_lo) / du for the tile centre's range l_c,
@@ -312,13 +316,22 @@ constexpr int kGatherBatch = 4;   // channels per weight batch
 // [f - s, f - s + 4), inside the window while f - s <= wpl - 4.
 // One (k_z block, tile) work item; tab = the scan's tile table; smem = the
 // workgroup's LDS (the weight slots, then the two row buffers).
+//
+// A channel's rows are copied into LDS by buffer loads that write LDS
+// directly: the descriptor's base is the channel's window start and its
+// size the rest of the channel, both scalar, so the copies take no vector
+// instructions; lanes whose chunk lies past the window (row padding that no
+// pixel reads) get an offset beyond the descriptor's size.  The batch of
+// NB channels is unrolled, so which buffer a channel uses is a constant.
 template <int KB, int RSC>
 __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __restrict__ q,
                                             const GatherTileEntry* __restrict__ tab, float2* __restrict__ G,
                                             int blk, int tile, unsigned char* smem) {
     constexpr int NW = kGatherWaves, RW = KB / NW, NB = kGatherBatch;
-    constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // DMA instructions per wavefront
+    constexpr int NIW = (KB * RSC + 64 * NW - 1) / (64 * NW);  // copy instructions per wavefront
     constexpr unsigned kBufBytes = KB * RSC * 16;
+    static_assert((KB * RSC) % 64 == 0, "every copy instruction fills 64 whole chunks");
+    static_assert(NB % 2 == 0, "a batch starts on the first row buffer");
     float4* wts = reinterpret_cast<float4*>(smem);   // [NB][2][64]
     constexpr unsigned lds_q = NB * 2 * 64 * 16;
 
@@ -330,26 +343,31 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const float kref_rev_f = static_cast<float>(kref_rev);
     const float inv_du_f = static_cast<float>(a.inv_du);
     const GatherTileEntry* tt = tab + static_cast<size_t>(tile) * a.n_ch;
+    // wavefront-uniform and immutable during the launch: read through the
+    // constant address space (scalar loads)
+    const const_tile_t ttc = reinterpret_cast<const_tile_t>(reinterpret_cast<unsigned long long>(tt));
 
-    // DMA chunk offsets (bytes from the channel's window start), ~0 = idle
+    // copy offsets (bytes from the channel's window start); 0x80000000 is
+    // beyond any descriptor size (a channel's profiles are under 2 GiB)
     unsigned doff[NIW];
 #pragma unroll
     for (int j = 0; j < NIW; ++j) {
         const int g = (wave + NW * j) * 64 + lane;
         const int r = g / RSC, k = g - r * RSC;
         const int kz = min(blk * KB + r, a.n_z - 1);
-        doff[j] = (r < KB && k < a.nchk) ? static_cast<unsigned>((kz * a.n_l + 2 * k) * 8) : ~0u;
+        doff[j] = (r < KB && k < a.nchk) ? static_cast<unsigned>((kz * a.n_l + 2 * k) * 8) : 0x80000000u;
     }
     const size_t chan_elems = static_cast<size_t>(a.n_z) * a.n_l;
-#define PL_STAGE_Q(C_, BUF_, WIN_)                                                                    \
-    do {                                                                                              \
-        const char* base_ = reinterpret_cast<const char*>(q + (C_) * chan_elems + (WIN_));           \
-        unsigned char* dst_ = smem + lds_q + (BUF_) * kBufBytes;                                      \
-        _Pragma("unroll") for (int j_ = 0; j_ < NIW; ++j_) {                                          \
-            const int i_ = wave + NW * j_;                                                            \
-            if (i_ * 64 < KB * RSC && doff[j_] != ~0u) PL_DMA16(base_ + doff[j_], dst_ + i_ * 1024);  \
-        }                                                                                             \
-    } while (0)
+    const unsigned chan_bytes = static_cast<unsigned>(chan_elems * 8);
+    auto stage = [&](int c, int buf, int win) {
+        const __amdgpu_buffer_rsrc_t rs = slab_rsrc(q + c * chan_elems + win, chan_bytes - 8u * win);
+        const lds_bytes_t dst = (lds_bytes_t)(smem + lds_q + buf * kBufBytes);  // generic to LDS address
+#pragma unroll
+        for (int j = 0; j < NIW; ++j) {
+            const int i = wave + NW * j;
+            if (i * 64 < KB * RSC) PL_LDS_COPY16(rs, dst + i * 1024, doff[j]);
+        }
+    };
 
     // this lane's pixel and its offset from the tile centre
     const int px = tx0 + (lane & 7), py = ty0 + (lane >> 3);
@@ -357,49 +375,38 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const float ox = ((lane & 7) - 3.5f) * static_cast<float>(a.dx), oy = ((lane >> 3) - 3.5f) * static_cast<float>(a.dy);
     const float oo = ox * ox + oy * oy;
 
-    // weights of (this lane's pixel, channel c) into slot [wave]:
-    // four tap weights, carrier, byte offset of the first tap in the row
+    // weights of (this lane's pixel, channel c) into slot [wave]: four tap
+    // weights, carrier, byte offset of the first tap in the row.  Lanes of
+    // pixels outside the image compute them like the others (their offset
+    // is clamped into the row; their sums are never written); a channel past
+    // the last one is never read.
     auto weights = [&](int c) {
-        float w[4] = {0.f, 0.f, 0.f, 0.f};
-        float cr = 0.f, ci = 0.f;
-        int off = 0;
-        if (c < a.n_ch && pvalid) {
-            // wavefront-uniform and immutable during the launch: read through
-            // the constant address space (scalar loads; device pass only)
-#if defined(__HIP_DEVICE_COMPILE__)
-            const GatherTileEntry e = *reinterpret_cast<const __attribute__((address_space(4))) GatherTileEntry*>(
-                reinterpret_cast<unsigned long long>(tt + c));
-#else
-            const GatherTileEntry e = tt[c];
-#endif
-            // range offset from the tile centre (see GatherTileEntry)
-            const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
-            float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
-            if (a.mono) {
-                dl += dl;
-            } else {
-                const float sR = 2.f * (e.xr * ox + e.yr * oy) + oo;
-                dl += sR * __builtin_amdgcn_rcpf(e.dr + __builtin_amdgcn_sqrtf(e.dr * e.dr + sR));
-            }
-            const float uu = e.uf + dl * inv_du_f;
-            const float fv = floorf(uu);
-            const float t = uu - fv;
-            // within the window by the bound above; the clamp keeps every read
-            // inside the staged row whatever the rounding
-            const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 4));
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
-            // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
-            const float2 c0 = cis_rev(kref_rev * e.lc);
-            const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
-            cr = c0.x * c1.x - c0.y * c1.y;
-            ci = c0.x * c1.y + c0.y * c1.x;
-            off = i0 * 8;
+        const GatherTileEntry e = ttc[min(c, a.n_ch - 1)];
+        // range offset from the tile centre (see GatherTileEntry)
+        const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
+        float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
+        if (a.mono) {
+            dl += dl;
+        } else {
+            const float sR = 2.f * (e.xr * ox + e.yr * oy) + oo;
+            dl += sR * __builtin_amdgcn_rcpf(e.dr + __builtin_amdgcn_sqrtf(e.dr * e.dr + sR));
         }
+        const float uu = e.uf + dl * inv_du_f;
+        const float fv = floorf(uu);
+        const float t = uu - fv;
+        // within the window by the bound above; the clamp keeps every read
+        // inside the staged row whatever the rounding
+        const int i0 = max(0, min(e.base + static_cast<int>(fv), wpl - 4));
+        float w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
+        // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
+        const float2 c0 = cis_rev(kref_rev * e.lc);
+        const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
         float4* slot = wts + wave * 2 * 64 + lane;
         slot[0] = make_float4(w[0], w[1], w[2], w[3]);
-        slot[64] = make_float4(cr, ci, __int_as_float(off), 0.f);
+        slot[64] = make_float4(c0.x * c1.x - c0.y * c1.y, c0.x * c1.y + c0.y * c1.x, __int_as_float(i0 * 8), 0.f);
     };
 
     float2 acc[RW];
@@ -407,29 +414,30 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     for (int r = 0; r < RW; ++r) acc[r] = make_float2(0.f, 0.f);
 
     __syncthreads();  // LDS free (the batch kernel reuses it per item)
-    PL_STAGE_Q(0, 0, tt[0].win);
+    stage(0, 0, ttc[0].win);
 
     const unsigned row0 = static_cast<unsigned>(wave * RW * RSC * 16);
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += NB) {
-        // window starts of the channels staged during this batch (lane k:
-        // channel c0 + 1 + k), one load per batch, read back by readlane
-        const int ck = c0 + 1 + lane;
-        const int wins = lane < NB && ck < a.n_ch ? tt[ck].win : 0;
+        // window starts of the channels staged during this batch (scalar
+        // loads, issued together)
+        int wn[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) wn[k] = ttc[min(c0 + 1 + k, a.n_ch - 1)].win;
         // the previous batch's slots are read (barrier at the end of its
         // last channel), so this batch's weights can take them
         weights(c0 + wave);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-#pragma unroll 1
+#pragma unroll
         for (int cc = 0; cc < NB; ++cc) {
             const int c = c0 + cc;
             if (c >= a.n_ch) break;
-            if (c + 1 < a.n_ch) PL_STAGE_Q(c + 1, (c + 1) & 1, __builtin_amdgcn_readlane(wins, cc));
+            if (c + 1 < a.n_ch) stage(c + 1, (cc + 1) & 1, wn[cc]);
             const float4* slot = wts + cc * 2 * 64 + lane;
             const float4 wa = slot[0], wb = slot[64];
             const unsigned off = __float_as_uint(wb.z);
-            const unsigned char* rp = smem + lds_q + (c & 1) * kBufBytes + row0 + off;
+            const unsigned char* rp = smem + lds_q + (cc & 1) * kBufBytes + row0 + off;
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 const float2* cp = reinterpret_cast<const float2*>(rp + r * RSC * 16);
@@ -452,7 +460,6 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
             __syncthreads();
         }
     }
-#undef PL_STAGE_Q
 
     if (pvalid) {
         float2* out = G + (static_cast<size_t>(py) * a.nx + px) * a.n_z;
@@ -463,7 +470,6 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
         }
     }
 }
-#undef PL_DMA16
 
 template <int KB, int RSC>
 __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(const float2* __restrict__ q,
@@ -608,6 +614,9 @@ int check_gather_plan(const HybridPlan& p, int rsc) {
     if (!p.bp_gather || (p.block != 32 && p.block != 64) || p.tile_x != 8 || p.tile_y != 8 || p.window % 2 ||
         nchk < 3 || nchk > p.window_pad || p.window_pad > rsc || 2 * nchk > p.n_l || p.waves != kGatherWaves)
         return fail(PL_EUNSUPPORTED, "pixel-per-lane back-projection: window %d, block %d", p.window, p.block);
+    // one channel's profiles are addressed by a 32-bit buffer descriptor
+    if (static_cast<unsigned long long>(p.n_z) * p.n_l * 8 >= (1ull << 31))
+        return fail(PL_EUNSUPPORTED, "range profiles of one channel exceed 2 GiB");
     return PL_OK;
 }
 

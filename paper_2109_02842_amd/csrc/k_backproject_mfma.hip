@@ -311,7 +311,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                 const int sr = __builtin_amdgcn_readlane(srw[g], cc * 16);
                 const unsigned char* ap = smem + bufo + a_lane + 2u * static_cast<unsigned>(sr);
                 if constexpr (SP) {
-                                        // B operand: the pixel's packed taps times the carrier,
+                    // B operand: the pixel's packed taps times the carrier,
                     // placed at this lane's 8 samples by byte permutes.  Rows
                     // of Re Q (kg < 2) take P = Re B for Re G and Q = Im B
                     // for Im G; rows of Im Q take -Q for Re G and P for Im G
@@ -329,7 +329,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                         vr[o] = __builtin_amdgcn_perm(rh1, rh0, sel[o]);
                         vi[o] = __builtin_amdgcn_perm(ih1, ih0, sel[o]);
                     }
-                                        const f16x8 br = __builtin_bit_cast(f16x8, vr), bi = __builtin_bit_cast(f16x8, vi);
+                    const f16x8 br = __builtin_bit_cast(f16x8, vr), bi = __builtin_bit_cast(f16x8, vi);
                     // every k_z tile's A fragment first, then the products:
                     // one wait for the LDS reads instead of one per tile
                     f16x8 va[KT];
@@ -344,7 +344,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                         accr[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va[t], br, accr[g][t], 0, 0, 0);
                         acci[g][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(va[t], bi, acci[g][t], 0, 0, 0);
                     }
-                                } else {
+                } else {
                     // B operand: taps of this lane's pixel times the carrier,
                     // placed at its 8 samples by byte permutes
                     const float xn = __shfl(xw[g], src), crn = __shfl(crw[g], src), cin = __shfl(ciw[g], src);
