@@ -491,13 +491,12 @@ int kz_ifft(const pl_geometry* geom, const pl_image_grid* grid, const float* spe
  * allocation owned by the batch; use the batch on that device only).
  * reconstruct_hybrid_batch takes arrays of n device pointers: echoes
  * ([c][m][f] complex64 per scan) and images ([z][y][x] complex64 per scan),
- * and a 256-byte-aligned device workspace of hybrid_batch_info's size.  The
- * per-scan steps of different scans run concurrently on up to four helper
- * streams the batch owns (default priority, created by make_hybrid_batch),
- * forked from and joined back into `stream` with events: the call's work
- * starts after, and later work on `stream` waits for, all of it.  It
- * allocates nothing and does not synchronise, so it may be captured in a
- * graph; calls on one batch, or sharing one workspace, must not overlap.
+ * and a 256-byte-aligned device workspace of hybrid_batch_info's size.  All
+ * of its work is launched in order on `stream` (per scan: plan tables, scan
+ * FFT, range compression; the back-projection launches; per scan: k_z
+ * IFFT).  It allocates nothing and does not synchronise, so it may be
+ * captured in a graph; calls on one batch, or sharing one workspace, must
+ * not overlap.
  * hybrid_batch_info: workspace bytes, scans in the persistent launch, its
  * work items and workgroups (any pointer may be NULL).
  * hybrid_batch_prepare writes every scan's plan tables (wavenumber tables,

@@ -4,12 +4,10 @@
 // of every scan that takes the pixel-per-lane kernel runs in ONE persistent
 // launch per LDS row length over (scan, k_z block, tile) work items,
 // heaviest scans first, in eight cost-balanced per-XCD queues with stealing.
-// The per-scan steps of different scans are independent: they run on a few
-// helper streams of the batch, forked from and joined back into the caller's
-// stream with events, so that small scans' kernels overlap.  The call
-// allocates nothing and does no host synchronisation, so a caller may
-// capture it in a graph (the helper streams join the capture through the
-// events).
+// Everything runs in order on the caller's stream (each launch fills the
+// GPU; overlapping different scans' steps on other streams was slower).  The
+// call allocates nothing and does no host synchronisation, so a caller may
+// capture it in a graph.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -32,20 +30,9 @@ struct pl_hybrid_batch {
     std::vector<Queue> queues;
     void* d_desc = nullptr;             // device: per-scan descriptors
     void* d_items = nullptr;            // device: per queue, int4 work items then 9 bounds
-    // helper streams (default priority) for the per-scan steps, and the
-    // fork / join events
-    static constexpr int kHelpers = 4;
-    int n_helpers = 0;
-    hipStream_t helpers[kHelpers] = {};
-    hipEvent_t fork = nullptr, joined[kHelpers] = {};
     ~pl_hybrid_batch() {
         if (d_desc) (void)hipFree(d_desc);
         if (d_items) (void)hipFree(d_items);
-        for (int h = 0; h < n_helpers; ++h) {
-            if (helpers[h]) (void)hipStreamDestroy(helpers[h]);
-            if (joined[h]) (void)hipEventDestroy(joined[h]);
-        }
-        if (fork) (void)hipEventDestroy(fork);
     }
 };
 
@@ -161,13 +148,6 @@ int make_hybrid_batch(int32_t n, const pl_geometry* const* geoms, const pl_image
          hipMemcpy(b->d_desc, desc.data(), desc.size(), hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(b->d_items, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
         return bail(fail(PL_EDEVICE, "make_hybrid_batch: uploading the work queues failed"));
-    b->n_helpers = std::min(n, static_cast<int>(pl_hybrid_batch::kHelpers));
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(PL_EDEVICE, "make_hybrid_batch: event creation failed"));
-    for (int h = 0; h < b->n_helpers; ++h)
-        if (hipStreamCreateWithFlags(&b->helpers[h], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&b->joined[h], hipEventDisableTiming) != hipSuccess)
-            return bail(fail(PL_EDEVICE, "make_hybrid_batch: helper stream creation failed"));
     *out = b;
     return PL_OK;
 }
@@ -229,43 +209,27 @@ int batch_impl(const pl_hybrid_batch* b, const float* const* echoes, float* cons
     for (int s = 0; s < n; ++s)
         if ((rc = b->geoms[s]->device_tables(&dts[s], stream))) return rc;
 
-    // fork: the helpers start after everything already on the caller's stream
-    auto fork = [&]() -> int {
-        if (hipEventRecord(b->fork, stream) != hipSuccess) return fail(PL_EDEVICE, "reconstruct_hybrid_batch: fork");
-        for (int h = 0; h < b->n_helpers; ++h)
-            if (hipStreamWaitEvent(b->helpers[h], b->fork, 0) != hipSuccess)
-                return fail(PL_EDEVICE, "reconstruct_hybrid_batch: fork");
-        return PL_OK;
-    };
-    // join: the caller's stream continues after every helper's work
-    auto join = [&]() -> int {
-        for (int h = 0; h < b->n_helpers; ++h)
-            if (hipEventRecord(b->joined[h], b->helpers[h]) != hipSuccess ||
-                hipStreamWaitEvent(stream, b->joined[h], 0) != hipSuccess)
-                return fail(PL_EDEVICE, "reconstruct_hybrid_batch: join");
-        return PL_OK;
-    };
-
-    // plan tables, scan FFT, range compression per scan, on the helpers
-    if ((rc = fork())) return rc;
+    // plan tables, scan FFT, range compression per scan, in order on the
+    // caller's stream: each of these launches fills the GPU by itself, and
+    // running several scans' steps at once on other streams made every
+    // kernel slower and the whole front end longer than the same steps in
+    // sequence (they contend for the CUs and evict each other's data)
     for (int s = 0; s < n; ++s) {
         const HybridPlan& p = b->plans[s];
-        hipStream_t hs = b->helpers[s % b->n_helpers];
         char* ws_s = w + b->ws_off[s];
         float2* spec = reinterpret_cast<float2*>(ws_s + p.off_spec);
-        if (tables && (rc = launch_plan_tables(p, dts[s], ws_s, hs))) return rc;
+        if (tables && (rc = launch_plan_tables(p, dts[s], ws_s, stream))) return rc;
         if ((rc = launch_scan_fft(b->geoms[s], reinterpret_cast<const float2*>(echoes[s]), spec, p.zfft,
-                                  ws_s + p.off_zfft, hs)))
+                                  ws_s + p.off_zfft, stream)))
             return rc;
         if (p.bp_mfma)
-            rc = launch_range_compress_mfma_split(p, spec, ws_s, reinterpret_cast<unsigned short*>(ws_s + p.off_q), hs);
+            rc = launch_range_compress_mfma_split(p, spec, ws_s, reinterpret_cast<unsigned short*>(ws_s + p.off_q), stream);
         else if (p.precision == PL_PREC_FP32)
-            rc = launch_range_compress_fp32(p, spec, ws_s, reinterpret_cast<float2*>(ws_s + p.off_q), hs);
+            rc = launch_range_compress_fp32(p, spec, ws_s, reinterpret_cast<float2*>(ws_s + p.off_q), stream);
         else
-            rc = launch_range_compress_mfma(p, spec, ws_s, reinterpret_cast<float2*>(ws_s + p.off_q), hs);
+            rc = launch_range_compress_mfma(p, spec, ws_s, reinterpret_cast<float2*>(ws_s + p.off_q), stream);
         if (rc) return rc;
     }
-    if ((rc = join())) return rc;
     // back-projection: the persistent launch, then any scan outside it
     for (size_t k = 0; k < b->queues.size(); ++k) {
         const auto& q = b->queues[k];
@@ -285,16 +249,14 @@ int batch_impl(const pl_hybrid_batch* b, const float* const* echoes, float* cons
                        : launch_backproject(p, dts[s], reinterpret_cast<const float2*>(ws_s + p.off_q), ws_s, G, stream);
         if (rc) return rc;
     }
-    // k_z inverse FFT per scan, on the helpers
-    if ((rc = fork())) return rc;
+    // k_z inverse FFT per scan
     for (int s = 0; s < n; ++s) {
         const HybridPlan& p = b->plans[s];
         char* ws_s = w + b->ws_off[s];
         if ((rc = launch_kz_ifft(p, reinterpret_cast<const float2*>(ws_s + p.off_G), reinterpret_cast<float2*>(images[s]),
-                                 ws_s + p.off_zfft, b->helpers[s % b->n_helpers])))
+                                 ws_s + p.off_zfft, stream)))
             return rc;
     }
-    if ((rc = join())) return rc;
     return PL_OK;
 }
 
