@@ -149,6 +149,9 @@ struct GatherTileEntry {
     float pad_;
 };
 static_assert(sizeof(GatherTileEntry) == 48, "tile table entry");
+// After the n_tiles * n_ch entries the tile table holds the centres'
+// carriers exp(j k_ref(b) l_c) for every k_z block b (float64 phase, range
+// reduced, then float32): float2 at ((b * n_tiles + tile) * n_ch + c).
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 size_t backproject_mfma_lds_bytes(int kz_block, bool single_pass);

@@ -299,10 +299,12 @@ constexpr int kGatherBatch = 4;   // channels per weight batch
 typedef __attribute__((address_space(3))) unsigned char* lds_bytes_t;
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef const __attribute__((address_space(4))) GatherTileEntry* const_tile_t;
+typedef const __attribute__((address_space(4))) float2* const_f2_t;
 #define PL_LDS_COPY16(RS, DST, VOFF) __builtin_amdgcn_raw_ptr_buffer_load_lds((RS), (DST), 16, (VOFF), 0, 0, 0)
 #else
 // host pass: parsed only, never run (the builtin is device-only)
 typedef const GatherTileEntry* const_tile_t;
+typedef const float2* const_f2_t;
 #define PL_LDS_COPY16(RS, DST, VOFF) ((void)(RS), (void)(DST), (void)(VOFF))
 #endif
 
@@ -339,13 +341,15 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpl = 2 * a.nchk;
-    const double kref_rev = a.kref[blk] * (0.5 / kPi);
-    const float kref_rev_f = static_cast<float>(kref_rev);
+    const float kref_rev_f = static_cast<float>(a.kref[blk] * (0.5 / kPi));
     const float inv_du_f = static_cast<float>(a.inv_du);
     const GatherTileEntry* tt = tab + static_cast<size_t>(tile) * a.n_ch;
+    const float2* tc = reinterpret_cast<const float2*>(tab + static_cast<size_t>(a.n_tiles) * a.n_ch) +
+                       (static_cast<size_t>(blk) * a.n_tiles + tile) * a.n_ch;
     // wavefront-uniform and immutable during the launch: read through the
     // constant address space (scalar loads)
     const const_tile_t ttc = reinterpret_cast<const_tile_t>(reinterpret_cast<unsigned long long>(tt));
+    const const_f2_t tcc = reinterpret_cast<const_f2_t>(reinterpret_cast<unsigned long long>(tc));
 
     // copy offsets (bytes from the channel's window start); 0x80000000 is
     // beyond any descriptor size (a channel's profiles are under 2 GiB)
@@ -381,7 +385,8 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
     // is clamped into the row; their sums are never written); a channel past
     // the last one is never read.
     auto weights = [&](int c) {
-        const GatherTileEntry e = ttc[min(c, a.n_ch - 1)];
+        const int ce = min(c, a.n_ch - 1);
+        const GatherTileEntry e = ttc[ce];
         // range offset from the tile centre (see GatherTileEntry)
         const float sT = 2.f * (e.xt * ox + e.yt * oy) + oo;
         float dl = sT * __builtin_amdgcn_rcpf(e.dt + __builtin_amdgcn_sqrtf(e.dt * e.dt + sT));
@@ -401,8 +406,8 @@ __device__ __forceinline__ void gather_tile(const BpgArgs& a, const float2* __re
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             w[j] = ((a.coef[j][3] * t + a.coef[j][2]) * t + a.coef[j][1]) * t + a.coef[j][0];
-        // carrier exp(j k_ref l): the centre's (float64 phase) times the offset's
-        const float2 c0 = cis_rev(kref_rev * e.lc);
+        // carrier exp(j k_ref l): the centre's (tile table) times the offset's
+        const float2 c0 = tcc[ce];
         const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
         float4* slot = wts + wave * 2 * 64 + lane;
         slot[0] = make_float4(w[0], w[1], w[2], w[3]);
@@ -483,17 +488,19 @@ __global__ __launch_bounds__(64 * kGatherWaves) void backproject_gather_kernel(c
 }
 
 struct TileTableArgs {
-    int n_ch, n_l, tiles_x, n_tiles, tile_x, tile_y, wpl;
-    int pad_;
+    int n_ch, n_l, tiles_x, n_tiles, tile_x, tile_y, wpl, n_blocks;
     double x0, y0, dx, dy, inv_du, reach;
+    double kref[kMaxBlocks];
 };
 
 // The tile table (see GatherTileEntry), one thread per (tile, channel): the
 // tile's centre, its range from the channel's antennas in float64, the
 // even start of the channel's staged window (wpl samples) and the centre's
-// first tap and fractional position relative to it.
+// first tap and fractional position relative to it; then the centre's
+// carrier for every k_z block (after the entries).
 __global__ void tile_table_kernel(TileTableArgs a, const double* __restrict__ chan, const double* __restrict__ llo,
                                   GatherTileEntry* __restrict__ tab) {
+    float2* carr = reinterpret_cast<float2*>(tab + static_cast<size_t>(a.n_tiles) * a.n_ch);
     const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
     for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < n;
          e += static_cast<long long>(gridDim.x) * blockDim.x) {
@@ -521,6 +528,8 @@ __global__ void tile_table_kernel(TileTableArgs a, const double* __restrict__ ch
         t.dr = static_cast<float>(dr);
         t.pad_ = 0.f;
         tab[e] = t;
+        for (int b = 0; b < a.n_blocks; ++b)
+            carr[(static_cast<size_t>(b) * a.n_tiles + tile) * a.n_ch + c] = cis_rev(a.kref[b] * (0.5 / kPi) * l);
     }
 }
 
@@ -714,8 +723,9 @@ size_t backproject_gather_lds_bytes(int rows, int row_chunks) {
 }
 
 size_t tile_table_bytes(const HybridPlan& p) {
-    return (p.bp_gather || p.bp_mfma) ? static_cast<size_t>(p.tiles_x) * p.tiles_y * p.n_ch * sizeof(GatherTileEntry)
-                                      : 0;
+    return (p.bp_gather || p.bp_mfma)
+               ? static_cast<size_t>(p.tiles_x) * p.tiles_y * p.n_ch * (sizeof(GatherTileEntry) + p.n_blocks * sizeof(float2))
+               : 0;
 }
 
 int launch_tile_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hipStream_t s) {
@@ -734,6 +744,8 @@ int launch_tile_tables(const HybridPlan& p, const DeviceTables& dt, char* ws, hi
     a.dy = p.dy;
     a.inv_du = 1.0 / p.du;
     a.reach = std::hypot((p.tile_x - 1) * p.dx, (p.tile_y - 1) * p.dy);  // 2 x the tile's half-diagonal
+    a.n_blocks = p.n_blocks;
+    for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
     const long long n = static_cast<long long>(a.n_tiles) * a.n_ch;
     const int blocks = static_cast<int>(std::min<long long>((n + 255) / 256, 8192));
     hipLaunchKernelGGL(tile_table_kernel, dim3(blocks), dim3(256), 0, s, a, dt.chan,

@@ -152,10 +152,12 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wpl = 8 * a.nck;  // staged samples per plane
-    const double kref_rev = a.kref[blk] * (0.5 / kPi);
-    const float kref_rev_f = static_cast<float>(kref_rev);
+    const float kref_rev_f = static_cast<float>(a.kref[blk] * (0.5 / kPi));
     const float inv_du_f = static_cast<float>(a.inv_du);
     const GatherTileEntry* tt = tab + static_cast<size_t>(tile) * a.n_ch;
+    // the tile centres' carriers of this k_z block (after the table's entries)
+    const float2* tc = reinterpret_cast<const float2*>(tab + static_cast<size_t>(a.n_tiles) * a.n_ch) +
+                       (static_cast<size_t>(blk) * a.n_tiles + tile) * a.n_ch;
 
     // selectors of the sample pairs (a, a+1), (a+2, a+3), (a+8, a+9),
     // (a+10, a+11) in tap units, a = a0 = 4h - d0, entry a0 + 15
@@ -232,7 +234,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
 
 #pragma unroll 1
     for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
-                // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
+        // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
         // each group and channel c0 + k: its range from the tile table
         // (float64 centre, float32 offset), its position in the group's
         // 16-sample window and its carrier; the MFMA lanes (pn, kg) of
@@ -246,7 +248,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
         {
             const int c = min(c0 + (lane >> 4), a.n_ch - 1);
             const GatherTileEntry e = tt[c];
-            const float2 cc0 = cis_rev(kref_rev * e.lc);   // the centre's carrier, float64 phase
+            const float2 cc0 = tc[c];   // the centre's carrier (float64 phase, in the table)
 #pragma unroll
             for (int g = 0; g < GPW; ++g) {
                 const bool ok = gpx[g] < a.nx && gpy[g] < a.ny;
@@ -268,7 +270,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                 m = min(m, __shfl_xor(m, 4));
                 m = min(m, __shfl_xor(m, 8));
                 const int sr = m == 0x3fffffff ? 0 : max(0, min(m & ~3, wpl - 16));
-                                srw[g] = sr;
+                srw[g] = sr;
                 const float2 c1 = cis_rev_f(kref_rev_f * dl);   // |dl| spans a tile: a few revolutions
                 const float cr = ok ? cc0.x * c1.x - cc0.y * c1.y : 0.f;
                 const float ci = ok ? cc0.x * c1.y + cc0.y * c1.x : 0.f;
