@@ -130,7 +130,7 @@ struct HybridPlan {
     // workspace layout (byte offsets, 256-aligned)
     size_t off_spec = 0, off_q = 0, off_G = 0, off_llo = 0, off_lref = 0, off_zfft = 0, off_tw_fine = 0;
     size_t off_deap = 0, off_kp = 0, off_wk = 0, off_krz = 0, off_mfma_a = 0, off_mfma_b = 0, off_tiles = 0,
-           off_qexp = 0, total = 0;
+           off_qexp = 0, off_part = 0, total = 0;
 };
 
 // Per (pixel tile, channel) geometry, computed once per call in float64
@@ -155,6 +155,10 @@ static_assert(sizeof(GatherTileEntry) == 48, "tile table entry");
 
 size_t backproject_lds_bytes(int n_ch, int rows, int window_pad);
 size_t backproject_mfma_lds_bytes(int kz_block, bool single_pass);
+// Partial spectra of the matrix-core back-projection's split tail items (at
+// most kMaxTailPieces pieces of a tile x k_z block each; 0 for other plans).
+constexpr int kMaxTailPieces = 1024;
+size_t backproject_mfma_part_bytes(const HybridPlan& p);
 size_t backproject_gather_lds_bytes(int rows, int row_chunks);
 
 // Batched pixel-per-lane back-projection (one persistent launch for several

@@ -37,6 +37,8 @@
 // result is multiplied by 2^g.  LDS rows are 17 chunks: Re in [0, 8), Im in
 // [8, 16), chunk 16 padding.  Each product then carries two FP16 roundings
 // (relative 2^-11 each) instead of the split form's FP32-class error.
+#include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "device.hpp"
@@ -65,6 +67,12 @@ constexpr int kSelEntries = 20;             // selector table: a0 = 4h - d0 in [
 
 struct BpmArgs {
     int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, mono;
+    // Work items [0, n_whole) run whole, on the first grid_whole workgroups
+    // (per_xcd per XCD); each later item is split into n_part pieces of
+    // whole groups of four channels (n_ch4 groups), one workgroup each, that
+    // write partial spectra to part (see tail_split).
+    int n_whole, grid_whole, n_part, n_ch4;
+    float2* part;
     const int* qexp;  // single-pass form: the profiles' scale exponent g
     double x0, y0, dx, dy, inv_du;
     float coef[4][4];  // tap j weight = sum_k coef[j][k] t^k, taps at floor(u) - 1 + j
@@ -144,8 +152,20 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
     u32x4* sel_tab = reinterpret_cast<u32x4*>(smem);
     constexpr unsigned lds0 = kSelEntries * 16;
 
-    const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-    if (work >= a.n_work) return;  // workgroup-uniform, before any barrier
+    // this workgroup's work item and channels [cb, ce) (workgroup-uniform;
+    // the returns come before any barrier)
+    int work, piece = -1, cb = 0, ce = a.n_ch;
+    if (static_cast<int>(blockIdx.x) < a.grid_whole) {
+        work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+        if (work >= a.n_whole) return;
+    } else {
+        piece = blockIdx.x - a.grid_whole;
+        if (piece >= (a.n_work - a.n_whole) * a.n_part) return;
+        const int part = piece % a.n_part;
+        work = a.n_whole + piece / a.n_part;
+        cb = 4 * (part * a.n_ch4 / a.n_part);   // a multiple of four: the batches and
+        ce = min(a.n_ch, 4 * ((part + 1) * a.n_ch4 / a.n_part));   // stage buffers line up
+    }
     const int blk = work / a.n_tiles;
     const int tile = work - blk * a.n_tiles;
     const int tx0 = (tile % a.tiles_x) * TX, ty0 = (tile / a.tiles_x) * TY;
@@ -211,11 +231,12 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
             acci[g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
 
-    // channel c's rows go to buffer (c / CPS) % 2 * CPS + c % CPS
+    // channel c's rows go to buffer (c / CPS) % 2 * CPS + c % CPS (cb is a
+    // multiple of 2 CPS, so the first channel takes buffer 0)
 #pragma unroll
     for (int k = 0; k < CPS; ++k)
-        if (k < a.n_ch)
-            PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + k * chan_elems + entry_win(tt + k)),
+        if (cb + k < ce)
+            PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + (cb + k) * chan_elems + entry_win(tt + cb + k)),
                           smem + lds0 + k * kBufBytes);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();  // selector table and the first channels' rows visible
@@ -233,7 +254,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
     asm volatile("" : "+v"(dq[0]), "+v"(dq[1]), "+v"(dq[2]));
 
 #pragma unroll 1
-    for (int c0 = 0; c0 < a.n_ch; c0 += 4) {
+    for (int c0 = cb; c0 < ce; c0 += 4) {
         // Geometry of the batch: lane (k = lane / 16, pn) takes pixel pn of
         // each group and channel c0 + k: its range from the tile table
         // (float64 centre, float32 offset), its position in the group's
@@ -296,12 +317,12 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
 #pragma unroll 1
         for (int cc = 0; cc < 4; ++cc) {
             const int c = c0 + cc;
-            if (c >= a.n_ch) break;
+            if (c >= ce) break;
             if (c % CPS == 0) {   // the next stage's channels, into the other buffers
 #pragma unroll
                 for (int k = 0; k < CPS; ++k) {
                     const int cn = c + CPS + k;
-                    if (cn < a.n_ch)
+                    if (cn < ce)
                         PL_STAGE_ROWS(reinterpret_cast<const char*>(qs + cn * chan_elems + entry_win(tt + cn)),
                                       smem + lds0 + (((cn / CPS) & 1) * CPS + k) * kBufBytes);
                 }
@@ -395,7 +416,7 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
                     }
                 }
             }
-            if (c % CPS == CPS - 1 || c + 1 == a.n_ch) {   // end of a stage (workgroup-uniform)
+            if (c % CPS == CPS - 1 || c + 1 == ce) {   // end of a stage (workgroup-uniform)
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
             }
@@ -404,6 +425,22 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
 
     // D layout: lane holds column (pixel) lane & 15, rows 4 (lane / 16) + v
     const float osc = SP ? ldexpf(1.f, a.qexp[kProfileScaleParts]) : 1.f;
+    if (piece >= 0) {
+        // a piece's partial spectrum of the tile: [pixel ly * TX + lx][k_z
+        // bin of the block], every pixel and bin (tail_combine_kernel keeps
+        // those inside the image and the scan)
+        float2* pp = a.part + static_cast<size_t>(piece) * (TX * TY * KB);
+#pragma unroll
+        for (int g = 0; g < GPW; ++g) {
+            float2* out = pp + ((gpy[g] - ty0) * TX + (gpx[g] - tx0)) * KB;
+#pragma unroll
+            for (int t = 0; t < KT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    out[16 * t + 4 * kg + v] = make_float2(accr[g][t][v] * osc, acci[g][t][v] * osc);
+        }
+        return;
+    }
 #pragma unroll
     for (int g = 0; g < GPW; ++g) {
         if (gpx[g] < a.nx && gpy[g] < a.ny) {
@@ -420,9 +457,46 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
     }
 }
 
+struct TailArgs {
+    int n_whole, n_part, n_tiles, tiles_x, tx, ty, kb, nx, ny, n_z;
+    long long n_elems;   // tail items x elements per piece
+};
+
+// Sum of the pieces' partial spectra of every split work item, in piece
+// order (deterministic), into the item's pixels and k_z bins of G.
+__global__ void tail_combine_kernel(const float2* __restrict__ part, TailArgs a, float2* __restrict__ G) {
+    const int tp = a.tx * a.ty * a.kb;   // elements per piece
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < a.n_elems;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int t = static_cast<int>(e / tp), r = static_cast<int>(e - static_cast<long long>(t) * tp);
+        const int lp = r / a.kb, lk = r - lp * a.kb;
+        const int work = a.n_whole + t;
+        const int blk = work / a.n_tiles, tile = work - blk * a.n_tiles;
+        const int gx = (tile % a.tiles_x) * a.tx + lp % a.tx, gy = (tile / a.tiles_x) * a.ty + lp / a.tx;
+        const int kz = blk * a.kb + lk;
+        if (gx >= a.nx || gy >= a.ny || kz >= a.n_z) continue;
+        const float2* src = part + static_cast<size_t>(t) * a.n_part * tp + r;
+        float2 acc = src[0];
+        for (int k = 1; k < a.n_part; ++k) {
+            const float2 v = src[static_cast<size_t>(k) * tp];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        G[(static_cast<size_t>(gy) * a.nx + gx) * a.n_z + kz] = acc;
+    }
+}
+
+// Tail split.  With S workgroups resident at once (occupancy x CUs), the
+// items beyond the last full round, T = n_work mod S of them, would run as
+// a round of their own with most of the GPU idle.  If T <= S / 2, each of
+// them is instead split into k = min(S / T, groups of four channels, the
+// workspace's pieces / T) pieces over its channels: the pieces fill that
+// round with work of 1 / k of an item each and write partial spectra, which
+// tail_combine_kernel adds (a second launch on the same stream).
 template <int GPW, int KT, int NW, bool SP>
-int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, const unsigned short* qs,
+int launch_cfg(BpmArgs a, size_t smem, long long cap_pieces, hipStream_t s, const unsigned short* qs,
                const GatherTileEntry* tab, float2* G) {
+    constexpr int NG = GPW * NW, GX = NG == 4 ? 2 : 4, TX = 4 * GX, TY = 4 * (NG / GX), KB = 16 * KT;
     auto fn = backproject_mfma_kernel<GPW, KT, NW, SP>;
     if (smem > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -430,14 +504,64 @@ int launch_cfg(const BpmArgs& a, size_t smem, unsigned blocks, hipStream_t s, co
         if (e != hipSuccess)
             return fail(PL_EDEVICE, "MFMA back-projection LDS of %zu bytes: %s", smem, hipGetErrorString(e));
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), smem, s, qs, tab, a, G);
-    return check_launch("back-projection (MFMA)");
+    static std::atomic<int> per_cu_cache{-1};   // this kernel's resident workgroups per CU
+    int per_cu = per_cu_cache.load(std::memory_order_relaxed);
+    if (per_cu < 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 64 * NW, smem) !=
+            hipSuccess)
+            return fail(PL_EDEVICE, "MFMA back-projection: occupancy query failed");
+        per_cu_cache.store(per_cu, std::memory_order_relaxed);
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(PL_EDEVICE, "MFMA back-projection: device query failed");
+    const long long slots = static_cast<long long>(per_cu) * cus;
+    a.n_whole = a.n_work;
+    a.n_part = 1;
+    if (slots > 0 && a.part) {
+        const long long tail = a.n_work % slots;
+        if (tail > 0 && 2 * tail <= slots) {
+            const long long k = std::min({slots / tail, static_cast<long long>(a.n_ch4), cap_pieces / tail});
+            if (k >= 2) {
+                a.n_whole = static_cast<int>(a.n_work - tail);
+                a.n_part = static_cast<int>(k);
+            }
+        }
+    }
+    a.per_xcd = (a.n_whole + 7) / 8;
+    a.grid_whole = 8 * a.per_xcd;
+    const long long blocks = a.grid_whole + static_cast<long long>(a.n_work - a.n_whole) * a.n_part;
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(64 * NW), smem, s, qs, tab, a, G);
+    int rc = check_launch("back-projection (MFMA)");
+    if (rc || a.n_part == 1) return rc;
+    TailArgs t{};
+    t.n_whole = a.n_whole;
+    t.n_part = a.n_part;
+    t.n_tiles = a.n_tiles;
+    t.tiles_x = a.tiles_x;
+    t.tx = TX;
+    t.ty = TY;
+    t.kb = KB;
+    t.nx = a.nx;
+    t.ny = a.ny;
+    t.n_z = a.n_z;
+    t.n_elems = static_cast<long long>(a.n_work - a.n_whole) * TX * TY * KB;
+    const unsigned cblocks = static_cast<unsigned>(std::min<long long>((t.n_elems + 255) / 256, 8192));
+    hipLaunchKernelGGL(tail_combine_kernel, dim3(cblocks), dim3(256), 0, s, a.part, t, G);
+    return check_launch("back-projection (MFMA) tail combine");
 }
 
 }  // namespace
 
 size_t backproject_mfma_lds_bytes(int kz_block, bool single_pass) {
     return kSelEntries * 16 + 2ull * stage_channels(single_pass, kz_block) * kz_block * 16 * row_chunks(single_pass);
+}
+
+size_t backproject_mfma_part_bytes(const HybridPlan& p) {
+    if (!p.bp_mfma) return 0;
+    const long long items = static_cast<long long>(p.tiles_x) * p.tiles_y * p.n_blocks;
+    const long long pieces = std::min<long long>(kMaxTailPieces, items * ((p.n_ch + 3) / 4));
+    return static_cast<size_t>(pieces) * p.tile_x * p.tile_y * p.block * sizeof(float2);
 }
 
 int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const unsigned short* qs, char* ws,
@@ -451,7 +575,8 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
     a.tiles_x = p.tiles_x;
     a.n_tiles = p.tiles_x * p.tiles_y;
     a.n_work = a.n_tiles * p.n_blocks;
-    a.per_xcd = (a.n_work + 7) / 8;
+    a.n_ch4 = (p.n_ch + 3) / 4;
+    a.part = reinterpret_cast<float2*>(ws + p.off_part);
     a.nck = p.window / 8;
     a.mono = p.mode == PL_MONO;
     a.qexp = reinterpret_cast<const int*>(ws + p.off_qexp);
@@ -466,16 +591,17 @@ int launch_backproject_mfma(const HybridPlan& p, const DeviceTables& dt, const u
         return fail(PL_EUNSUPPORTED, "MFMA back-projection window %d out of range", p.window);
     const size_t smem = backproject_mfma_lds_bytes(p.block, p.bp_mfma_sp);
     if (smem > kMaxLds) return fail(PL_EUNSUPPORTED, "MFMA back-projection needs %zu bytes of LDS", smem);
-    const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const GatherTileEntry* tab = reinterpret_cast<const GatherTileEntry*>(ws + p.off_tiles);
     (void)dt;
+    const long long cap_pieces =
+        static_cast<long long>(backproject_mfma_part_bytes(p) / (static_cast<size_t>(p.tile_x) * p.tile_y * p.block * sizeof(float2)));
     const int ng = p.tile_x * p.tile_y / 16;
     const int kt = p.block / 16;
     const int nw = p.waves;
 #define PL_BPM(G_, K_, W_)                                                                              \
     if (ng == G_ * W_ && kt == K_ && nw == W_)                                                          \
-        return p.bp_mfma_sp ? launch_cfg<G_, K_, W_, true>(a, smem, blocks, s, qs, tab, G)               \
-                            : launch_cfg<G_, K_, W_, false>(a, smem, blocks, s, qs, tab, G);
+        return p.bp_mfma_sp ? launch_cfg<G_, K_, W_, true>(a, smem, cap_pieces, s, qs, tab, G)           \
+                            : launch_cfg<G_, K_, W_, false>(a, smem, cap_pieces, s, qs, tab, G);
     PL_BPM(1, 4, 4) PL_BPM(1, 8, 4) PL_BPM(2, 4, 4) PL_BPM(2, 8, 4) PL_BPM(4, 4, 4) PL_BPM(4, 8, 4)
     PL_BPM(1, 4, 8) PL_BPM(1, 8, 8) PL_BPM(2, 4, 8)
 #undef PL_BPM

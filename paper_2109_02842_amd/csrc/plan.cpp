@@ -418,6 +418,7 @@ int make_plan(const pl_geometry* g, const pl_image_grid* grid, const pl_hybrid_o
     p.off_wk = take(nz * nf * 4);
     p.off_krz = take(nz * 8);
     p.off_tiles = take(tile_table_bytes(p));
+    p.off_part = take(backproject_mfma_part_bytes(p));
     p.n_chp = (p.n_ch + 31) / 32 * 32;
     p.n_fp = (p.n_f + 15) / 16 * 16;
     if (p.precision != PL_PREC_FP32) {
