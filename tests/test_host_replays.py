@@ -11,7 +11,10 @@ inside the buffer the kernel stages or owns:
 * adjoint back-projection: the tiles a (channel, range segment) workgroup
   lists include every pixel whose taps reach the segment;
 * NUFFT spreading: the fine-grid cells a (channel, k_z) pair fills lie within
-  one period of the grid on either side and number at most one period.
+  one period of the grid on either side and number at most one period;
+* matrix-core back-projection tail split: the pieces of a split work item
+  cover its channels exactly once in runs that start at multiples of four,
+  and the split fills at most the resident workgroups and the workspace.
 """
 import math
 from dataclasses import replace
@@ -191,3 +194,39 @@ def test_nufft_cells_stay_within_one_period(case, opts):
             khi = math.floor(p[-1] + h)
             assert -N <= klo and khi < 2 * N, (wl.name, kap, klo, khi, N)
             assert khi - klo + 1 <= N, (wl.name, kap)        # no cell is filled twice
+
+
+# ------------------------------------------- matrix-core tail split pieces
+def _tail_split(n_work, slots, n_ch, cap_pieces):
+    """The launcher's choice: (whole items, pieces per tail item)."""
+    n_ch4 = (n_ch + 3) // 4
+    tail = n_work % slots
+    if tail > 0 and 2 * tail <= slots:
+        k = min(slots // tail, n_ch4, cap_pieces // tail)
+        if k >= 2:
+            return n_work - tail, k
+    return n_work, 1
+
+
+def _piece_channels(part, k, n_ch):
+    n_ch4 = (n_ch + 3) // 4
+    return 4 * (part * n_ch4 // k), min(n_ch, 4 * ((part + 1) * n_ch4 // k))
+
+
+@pytest.mark.parametrize("n_work,slots,n_ch", [(676, 512, 320), (256, 512, 320), (768, 512, 896), (2048, 512, 896),
+                                                (8, 512, 48), (3, 512, 5), (1300, 512, 320), (5, 1024, 7)])
+def test_tail_split_pieces_cover_channels_once(n_work, slots, n_ch):
+    cap = min(1024, n_work * ((n_ch + 3) // 4))      # pieces the workspace holds
+    n_whole, k = _tail_split(n_work, slots, n_ch, cap)
+    tail = n_work - n_whole
+    if k > 1:
+        assert n_whole % slots == 0 and 0 < tail < slots    # whole rounds, then the split tail
+        assert tail * k <= slots and tail * k <= cap    # one round, within the workspace
+        assert 2 * tail <= slots
+    else:
+        assert n_whole == n_work
+    for part in range(k):
+        cb, ce = _piece_channels(part, k, n_ch)
+        assert cb % 4 == 0 and cb < ce <= n_ch
+    covered = [c for part in range(k) for c in range(*_piece_channels(part, k, n_ch))]
+    assert covered == list(range(n_ch))
