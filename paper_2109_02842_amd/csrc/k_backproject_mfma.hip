@@ -69,9 +69,10 @@ struct BpmArgs {
     int n_ch, n_z, n_l, nx, ny, tiles_x, n_tiles, n_work, per_xcd, nck, mono;
     // Work items [0, n_whole) run whole, on the first grid_whole workgroups
     // (per_xcd per XCD); each later item is split into n_part pieces of
-    // whole groups of four channels (n_ch4 groups), one workgroup each, that
-    // write partial spectra to part (see tail_split).
-    int n_whole, grid_whole, n_part, n_ch4;
+    // whole groups of four channels (n_ch4 groups), one workgroup each
+    // (per_xcd_tail per XCD, in (item, piece) order), that write partial
+    // spectra to part (see the tail split at launch_cfg).
+    int n_whole, grid_whole, n_part, n_ch4, per_xcd_tail;
     float2* part;
     const int* qexp;  // single-pass form: the profiles' scale exponent g
     double x0, y0, dx, dy, inv_du;
@@ -159,7 +160,8 @@ void backproject_mfma_kernel(const unsigned short* __restrict__ qs, const Gather
         work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
         if (work >= a.n_whole) return;
     } else {
-        piece = blockIdx.x - a.grid_whole;
+        const int bt = blockIdx.x - a.grid_whole;
+        piece = (bt & 7) * a.per_xcd_tail + (bt >> 3);   // a contiguous share per XCD
         if (piece >= (a.n_work - a.n_whole) * a.n_part) return;
         const int part = piece % a.n_part;
         work = a.n_whole + piece / a.n_part;
@@ -530,7 +532,8 @@ int launch_cfg(BpmArgs a, size_t smem, long long cap_pieces, hipStream_t s, cons
     }
     a.per_xcd = (a.n_whole + 7) / 8;
     a.grid_whole = 8 * a.per_xcd;
-    const long long blocks = a.grid_whole + static_cast<long long>(a.n_work - a.n_whole) * a.n_part;
+    a.per_xcd_tail = static_cast<int>((static_cast<long long>(a.n_work - a.n_whole) * a.n_part + 7) / 8);
+    const long long blocks = a.grid_whole + 8LL * a.per_xcd_tail;
     hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(64 * NW), smem, s, qs, tab, a, G);
     int rc = check_launch("back-projection (MFMA)");
     if (rc || a.n_part == 1) return rc;

@@ -230,3 +230,8 @@ def test_tail_split_pieces_cover_channels_once(n_work, slots, n_ch):
         assert cb % 4 == 0 and cb < ce <= n_ch
     covered = [c for part in range(k) for c in range(*_piece_channels(part, k, n_ch))]
     assert covered == list(range(n_ch))
+    # the tail's workgroups: XCD b % 8 takes a contiguous share of the pieces
+    n_pieces = tail * k if k > 1 else 0
+    per_xcd_tail = (n_pieces + 7) // 8
+    pieces = [(b & 7) * per_xcd_tail + (b >> 3) for b in range(8 * per_xcd_tail)]
+    assert sorted(q for q in pieces if q < n_pieces) == list(range(n_pieces))
