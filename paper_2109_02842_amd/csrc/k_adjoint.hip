@@ -191,11 +191,17 @@ constexpr int kAdjWaves = 4;
 constexpr int kAdjSeg = 32;    // range samples per workgroup
 constexpr int kAdjBins = 64;   // k_z bins per workgroup, one per lane
 
-struct AdjRec {                // one ranked pixel of a tile
-    float4 w;                  // tap weights
-    float4 car;                // carrier of bins [0, 32) (x, y) and [32, 64) (z, w) of the workgroup
-    int pix, i0, pad0, pad1;   // pixel index, first tap relative to the segment
-};
+// G~ through a buffer descriptor: the pixel's row offset is scalar, the
+// lane's bin a fixed per-lane offset, and a lane past the last bin reads
+// beyond the descriptor (zero) instead of branching.
+typedef unsigned int adj_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t adj_rsrc(const float2* p, unsigned bytes) {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(a >> 32));
+    void* u = reinterpret_cast<void*>((static_cast<unsigned long long>(hi) << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, 0, __builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
 
 __device__ __forceinline__ double rect_dist(double px, double py, double x0, double x1, double y0, double y1) {
     const double cx = fmin(fmax(px, x0), x1), cy = fmin(fmax(py, y0), y1);
@@ -209,7 +215,12 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
     constexpr int S = kAdjSeg, NW = kAdjWaves, NT = 64 * NW;
     __shared__ int tiles[NT];
     __shared__ int wcount[NW];
-    __shared__ AdjRec rec[NW][64];
+    // the ranked pixels of a tile, per wavefront: tap weights, the carriers
+    // of bins [0, 32) and [32, 64) of the workgroup, (pixel, first tap
+    // relative to the segment)
+    __shared__ float4 rw[NW][64];
+    __shared__ float2 rc[NW][2][64];
+    __shared__ int2 rpi[NW][64];
     __shared__ float sum_re[S][65], sum_im[S][65];   // odd row length: a lane per bank
 
     const int work = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
@@ -229,7 +240,12 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
     const double kr1 = a.kref[min(kz0 + 32, a.n_z - 1) / a.block] * (0.5 / kPi);
     const int kz = kz0 + lane;
     const bool kok = kz < a.n_z;
-    AdjRec* myrec = rec[wave];
+    float4* myw = rw[wave];
+    float2* myc = rc[wave][lane >> 5];   // this lane's half of the bins
+    int2* mypi = rpi[wave];
+    const __amdgpu_buffer_rsrc_t grs =
+        adj_rsrc(Gt, static_cast<unsigned>(static_cast<size_t>(a.nx) * a.ny * a.n_z * sizeof(float2)));
+    const unsigned gvoff = kok ? static_cast<unsigned>(kz) * 8u : 0x80000000u;
 
     // the lane's copy of the segment, real and imaginary parts apart (each
     // array stays in registers under a wavefront-uniform index)
@@ -275,8 +291,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
             const int tt = tiles[k];
             // lane = pixel of the tile
             const int px = (tt % a.tiles_x) * 8 + (lane & 7), py = (tt / a.tiles_x) * 8 + (lane >> 3);
-            int i0 = 1 << 20;
-            AdjRec r{};
+            int i0 = 1 << 20, pix = 0;
+            float4 rwv = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 c0 = make_float2(0.f, 0.f), c1 = c0;
             if (px < a.nx && py < a.ny) {
                 const double xg = a.x0 + px * a.dx, yg = a.y0 + py * a.dy;
                 const double l = sqrt((xg - xT) * (xg - xT) + (yg - yT) * (yg - yT)) +
@@ -284,15 +301,14 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
                 const double u = (l - l0) * a.inv_du;
                 const double fl = floor(u);
                 const float tf = static_cast<float>(u - fl);
-                r.w.x = ((a.coef[0][3] * tf + a.coef[0][2]) * tf + a.coef[0][1]) * tf + a.coef[0][0];
-                r.w.y = ((a.coef[1][3] * tf + a.coef[1][2]) * tf + a.coef[1][1]) * tf + a.coef[1][0];
-                r.w.z = ((a.coef[2][3] * tf + a.coef[2][2]) * tf + a.coef[2][1]) * tf + a.coef[2][0];
-                r.w.w = ((a.coef[3][3] * tf + a.coef[3][2]) * tf + a.coef[3][1]) * tf + a.coef[3][0];
-                const float2 c0 = cis_rev(kr0 * l), c1 = cis_rev(kr1 * l);
-                r.car = make_float4(c0.x, c0.y, c1.x, c1.y);
+                rwv.x = ((a.coef[0][3] * tf + a.coef[0][2]) * tf + a.coef[0][1]) * tf + a.coef[0][0];
+                rwv.y = ((a.coef[1][3] * tf + a.coef[1][2]) * tf + a.coef[1][1]) * tf + a.coef[1][0];
+                rwv.z = ((a.coef[2][3] * tf + a.coef[2][2]) * tf + a.coef[2][1]) * tf + a.coef[2][0];
+                rwv.w = ((a.coef[3][3] * tf + a.coef[3][2]) * tf + a.coef[3][1]) * tf + a.coef[3][0];
+                c0 = cis_rev(kr0 * l);
+                c1 = cis_rev(kr1 * l);
                 i0 = static_cast<int>(fl) - 1 - s0;
-                r.pix = py * a.nx + px;
-                r.i0 = i0;
+                pix = py * a.nx + px;
             }
             const bool valid = i0 >= -3 && i0 < S;
             const unsigned long long vm = __ballot(valid);
@@ -311,27 +327,33 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
                 if (valid && i0 == v) rank = placed + __popcll(m & ((1ull << lane) - 1ull));
                 placed += __popcll(m);
             }
-            if (valid) myrec[rank] = r;
+            if (valid) {
+                myw[rank] = rwv;
+                rc[wave][0][rank] = c0;
+                rc[wave][1][rank] = c1;
+                mypi[rank] = make_int2(pix, i0);
+            }
             wave_lds_sync();   // the records, written by their lanes, read by every lane below
 
             // lane = k_z bin: walk the ranked pixels
             float2 a0 = make_float2(0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
-            int cur = __builtin_amdgcn_readfirstlane(myrec[0].i0);
+            int cur = __builtin_amdgcn_readfirstlane(mypi[0].y);
 #pragma unroll 1
             for (int q0 = 0; q0 < n; q0 += 8) {
-                // the next eight pixels' G~ first, so their latency is paid once
-                float2 gv[8];
+                // the next eight pixels' G~ first, so their latency is paid
+                // once (entries past n hold an earlier tile's pixels or
+                // nothing: what they load is never used, and a row offset
+                // past G~ reads zeros)
+                adj_u32x2 gv[8];
 #pragma unroll
                 for (int qq = 0; qq < 8; ++qq) {
-                    const int q = min(q0 + qq, n - 1);
-                    const int pix = __builtin_amdgcn_readfirstlane(myrec[q].pix);
-                    gv[qq] = kok ? Gt[static_cast<size_t>(pix) * a.n_z + kz] : make_float2(0.f, 0.f);
+                    const unsigned pix = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(mypi[q0 + qq].x));
+                    gv[qq] = __builtin_amdgcn_raw_buffer_load_b64(grs, gvoff, pix * static_cast<unsigned>(a.n_z) * 8u, 0);
                 }
 #pragma unroll
                 for (int qq = 0; qq < 8; ++qq) {
                     if (q0 + qq >= n) break;  // wavefront-uniform
-                    const AdjRec& pr = myrec[q0 + qq];
-                    const int pi0 = __builtin_amdgcn_readfirstlane(pr.i0);
+                    const int pi0 = __builtin_amdgcn_readfirstlane(mypi[q0 + qq].y);
                     while (cur < pi0) {  // samples before this pixel's first tap are complete
                         if (cur >= 0 && cur < S) {
                             acr[cur] += a0.x;
@@ -343,10 +365,11 @@ __global__ __launch_bounds__(64 * kAdjWaves) void backproject_adjoint_kernel(con
                         a3 = make_float2(0.f, 0.f);
                         ++cur;
                     }
-                    const float4 w = pr.w, car = pr.car;
-                    const float cr = lane < 32 ? car.x : car.z, ci = lane < 32 ? car.y : car.w;
+                    const float4 w = myw[q0 + qq];
+                    const float2 car = myc[q0 + qq];
+                    const float gr = __uint_as_float(gv[qq].x), gi = __uint_as_float(gv[qq].y);
                     // conj(carrier) * G~
-                    const float hr = cr * gv[qq].x + ci * gv[qq].y, hi = cr * gv[qq].y - ci * gv[qq].x;
+                    const float hr = car.x * gr + car.y * gi, hi = car.x * gi - car.y * gr;
                     a0.x = fmaf(w.x, hr, a0.x);
                     a0.y = fmaf(w.x, hi, a0.y);
                     a1.x = fmaf(w.y, hr, a1.x);
@@ -449,6 +472,9 @@ int launch_backproject_adjoint(const HybridPlan& p, const DeviceTables& dt, cons
     a.inv_du = 1.0 / p.du;
     std::memcpy(a.coef, p.coef, sizeof(a.coef));
     for (int b = 0; b < kMaxBlocks; ++b) a.kref[b] = p.kref[b];
+    // G~ is read through one buffer descriptor (32-bit offsets)
+    if (static_cast<unsigned long long>(p.nx) * p.ny * p.n_z * 8 >= (1ull << 31))
+        return fail(PL_EUNSUPPORTED, "adjoint back-projection: the spectrum exceeds 2 GiB");
     const unsigned blocks = static_cast<unsigned>(8 * a.per_xcd);
     const double* llo = reinterpret_cast<const double*>(ws + p.off_llo);
     hipLaunchKernelGGL(backproject_adjoint_kernel, dim3(blocks), dim3(64 * kAdjWaves), 0, s, Gt, dt.chan, llo, a, qt);

@@ -362,6 +362,30 @@ def test_mfma_single_pass_tilings(tile, tile_y, kb, waves):
     assert err < 1e-3
 
 
+@pytest.mark.parametrize("precision,mbp", [("fp16", 2), ("bf16", 1)])
+def test_mfma_tail_split_is_repeatable(precision, mbp):
+    # 4 x 3 tiles x 5 k_z blocks = 60 work items, fewer than half the
+    # resident workgroups: the launch splits every item over its channels
+    # and adds the pieces' partial spectra in a fixed order, so two calls
+    # give the same bits (and the result holds the oracle's bar)
+    arr_desc = replace(W.C1.array, n_scan=300)
+    grid = _fine_grid(61, 45, 0.0015)
+    g = pr.make_geometry(arr_desc)
+    s = W.random_echo(arr_desc, 57)
+    say("mfma tail split repeatability", precision, mbp)
+    a = pr.reconstruct_hybrid(g, grid, dev(s), precision=precision, mfma_backprojection=mbp)
+    b = pr.reconstruct_hybrid(g, grid, dev(s), precision=precision, mfma_backprojection=mbp)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    kap = [0, 64, 150, 299]
+    pix = np.unique(np.concatenate([W.random_subset(grid.nx * grid.ny, 120, 58), [0, grid.nx * grid.ny - 1]]))
+    px, py = ohyb.pixel_grid(grid)
+    ref = ohyb.spectrum_at(ogeom.build(arr_desc), ohyb.scan_spectrum(s), kap, px[pix], py[pix])
+    err = rel(_spectrum_subset(host(a), kap, pix), ref)
+    say("   rel L2", err)
+    assert err < 1e-3
+
+
 @pytest.mark.parametrize("scale", [1e-15, 1.0, 1e15])
 def test_mfma_single_pass_follows_the_data_scale(scale):
     # the FP16 profiles' power-of-two scale comes from the data: echoes 15
