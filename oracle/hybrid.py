@@ -27,6 +27,10 @@ Readings of the paper used here:
     then the scan grid: the offset of the scan origin cancels between the two
     transforms.
   * The measure "k dk" becomes the weight k_f; the constant dk is dropped.
+    Parity unpinned for this factor: no value the paper prints or closed
+    form it gives fixes the weight (leaving it out tapers the image's
+    amplitude smoothly in range and moves no peak), so only the GPU parity
+    tests tie the GPU's weight to this one.
   * Amplitude and constant-phase factors of the stationary-phase results are
     omitted (the paper omits them), so the image scale is fixed by the weight.
   * Evanescent terms (k_rho^2 < 0) are dropped.
