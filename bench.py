@@ -245,6 +245,32 @@ def make_timers(pr, torch, W, wl, geom, echo, img):
     return time_path, parity
 
 
+def time_adjoint(pr, torch, geom, grid, img, steps, warmup, base=None):
+    """ms per adjoint_hybrid call (image -> echo) of the FP32 plan with the
+    pixel-per-lane back-projection (other options from ``base``), or None if
+    that plan takes another kernel; same workspace size as the
+    reconstruction, one call per step."""
+    aopts = dict(base or {}, precision="fp32", mfma_backprojection=0, range_method="nufft")
+    aplan = pr.hybrid_plan_info(geom, grid, **aopts)
+    if aplan.bp_kernel != "pixel-lanes":
+        return None
+    aws = pr.workspace(aplan.workspace_bytes)
+    aout = torch.empty(geom.echo_shape, dtype=torch.complex64, device="cuda")
+    for _ in range(warmup + 1):
+        pr.adjoint_hybrid(geom, grid, img, out=aout, ws=aws, **aopts)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        pr.adjoint_hybrid(geom, grid, img, out=aout, ws=aws, **aopts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del aws, aout
+    return ms
+
+
 def bench_c3(args, torch, pr, W):
     """The multistatic workload (C3) in the same run: the FP32 path and the
     single-pass FP16 matrix-core path, each timed like the headline (plan
@@ -272,6 +298,12 @@ def bench_c3(args, torch, pr, W):
         res[name] = r
         log(f"[bench] C3 {name}: {ms:.3f} ms/step ({voxels / (ms * 1e-3):.3e} voxels/s); "
             f"rel L2 {r.get('rel_l2_vs_oracle', float('nan')):.2e}")
+    if not args.no_variants:
+        ams = time_adjoint(pr, torch, geom, wl.grid, img, steps, 2)
+        if ams is not None:
+            res["adjoint"] = {"ms_per_call": ams, "voxels_per_s": voxels / (ams * 1e-3),
+                              "note": "image -> echo, FP32, NUFFT plan with the pixel-per-lane kernel"}
+            log(f"[bench] C3 adjoint: {ams:.3f} ms per call")
     del echo, img
     torch.cuda.empty_cache()
     return res
@@ -415,28 +447,12 @@ def main() -> int:
                 f"peak error {v.get('peak_position_error_voxels', float('nan')):.2f} voxels")
 
     if not args.no_variants:
-        # the adjoint (image -> echo) of the FP32 pixel-per-lane plan: one
-        # call per step, the same workspace size as the reconstruction
-        aopts = dict(opts, precision="fp32", mfma_backprojection=0, range_method="nufft")
-        aplan = pr.hybrid_plan_info(geom, wl.grid, **aopts)
-        if aplan.bp_kernel == "pixel-lanes":
-            aws = pr.workspace(aplan.workspace_bytes)
-            aout = torch.empty(geom.echo_shape, dtype=torch.complex64, device="cuda")
-            for _ in range(args.warmup + 1):
-                pr.adjoint_hybrid(geom, wl.grid, img, out=aout, ws=aws, **aopts)
-            torch.cuda.synchronize()
-            stream = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(args.steps):
-                pr.adjoint_hybrid(geom, wl.grid, img, out=aout, ws=aws, **aopts)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ams = e0.elapsed_time(e1) / args.steps
+        # the adjoint (image -> echo) of the FP32 pixel-per-lane plan
+        ams = time_adjoint(pr, torch, geom, wl.grid, img, args.steps, args.warmup, opts)
+        if ams is not None:
             out["adjoint"] = {"ms_per_call": ams, "voxels_per_s": voxels / (ams * 1e-3),
                               "note": "image -> echo, FP32, NUFFT plan with the pixel-per-lane kernel"}
             log(f"[bench] adjoint: {ams:.3f} ms per call")
-            del aws
 
     if not args.no_bp:
         nz = max(1, min(args.bp_planes, a.n_scan))
