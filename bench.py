@@ -57,6 +57,22 @@ def stage_rooflines(plan, a, wl, geom, stage, args):
     return out
 
 
+def bp_roofline(plan, terms: int, bp_ms: float) -> dict:
+    """The back-projection's algorithmic FLOP rate over its event-timed
+    launch against the roof of the unit it runs on: the FP32 vector peak for
+    the VALU kernels, the dense BF16 / FP16 matrix-core peak for the MFMA
+    kernels (which issue 6 (split) or 2 (single pass) MFMA 16x16x32 per
+    (4x4 pixels, 16 k_z, channel); that rate is reported as issued_tflops)."""
+    achieved = FLOP_PER_TERM * terms / (bp_ms * 1e-3) / 1e12
+    if plan.mfma_backprojection:
+        n_mfma = 2 if plan.bp_kernel == "mfma-1pass" else 6
+        return {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "issued_tflops": n_mfma * 2 * 16 * 16 * 32 / 256 * terms / (bp_ms * 1e-3) / 1e12}
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+
+
 def measured_traffic(kernel: str, workload: str, precision: str, n_l: int):
     """HBM bytes per back-projection launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if there is none for this
@@ -300,7 +316,9 @@ def bench_c3(args, torch, pr, W):
     for name, opts in paths:
         ms, stage, _, med, plan = time_path(opts, steps, 2, min_warm_s=0.3)
         res[name] = {"value": voxels / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": ms, "median_ms": med,
-                     "steps": steps, "stages_ms": stage, "bp_kernel": plan.bp_kernel}
+                     "steps": steps, "stages_ms": stage, "bp_kernel": plan.bp_kernel,
+                     "roofline": bp_roofline(plan, a.n_scan * wl.grid.nx * wl.grid.ny * geom.n_channels,
+                                             stage["backproject"])}
         log(f"[bench] C3 {name}: {ms:.3f} ms/step ({voxels / (ms * 1e-3):.3e} voxels/s)")
     if not args.no_variants:
         ams = time_adjoint(pr, torch, geom, wl.grid, img, steps, 2)
@@ -399,18 +417,7 @@ def main() -> int:
     value = voxels / (ms * 1e-3)
     terms = a.n_scan * wl.grid.nx * wl.grid.ny * geom.n_channels
     bp_ms = stage["backproject"]
-    achieved = FLOP_PER_TERM * terms / (bp_ms * 1e-3) / 1e12
-    if plan.mfma_backprojection:
-        # algorithmic flops against the dense BF16 / FP16 matrix-core peak;
-        # the kernel issues 6 (split) or 2 (single pass) MFMA 16x16x32 per
-        # (4x4 pixels, 16 k_z, channel)
-        n_mfma = 2 if plan.bp_kernel == "mfma-1pass" else 6
-        roof = {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS,
-                "frac": achieved / BF16_MFMA_PEAK_TFLOPS,
-                "issued_tflops": n_mfma * 2 * 16 * 16 * 32 / 256 * terms / (bp_ms * 1e-3) / 1e12}
-    else:
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS}
+    roof = bp_roofline(plan, terms, bp_ms)
     out = {
         "metric": METRIC, "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -420,7 +427,7 @@ def main() -> int:
                    "path": f"hybrid-{'NUFFT' if args.range_method == 'nufft' else 'resample'} {args.precision}",
                    "interp": args.interp, "l_oversample": args.l_oversample, "nufft_tol": 1e-6,
                    "tile": list(plan.tile), "kz_block": plan.block},
-        "roofline": dict(roof, unit="TFLOP/s",
+        "roofline": dict(roof,
                          traffic=measured_traffic(plan.bp_kernel, args.config, args.precision, plan.n_l),
                          kernel="backproject", flop_per_launch=FLOP_PER_TERM * terms, avg_launch_ms=bp_ms),
         "stages_ms": stage,
@@ -442,9 +449,10 @@ def main() -> int:
             vopts = dict(opts, precision=prec, mfma_backprojection=mbp, range_method=rm)
             if mbp:
                 vopts.update(tile=0, tile_y=0, kz_block=0, kz_per_lane=0, waves=0)
-            vms, vstage, _, vmed, _ = time_path(vopts, args.steps, 1)
+            vms, vstage, _, vmed, vplan = time_path(vopts, args.steps, 1)
             out["variants"][name] = {"value": voxels / (vms * 1e-3), "ms_per_step": vms, "stages_ms": vstage,
-                                     "speedup_vs_main": ms / vms}
+                                     "speedup_vs_main": ms / vms, "bp_kernel": vplan.bp_kernel,
+                                     "roofline": bp_roofline(vplan, terms, vstage["backproject"])}
             vopts_of[name] = vopts
             log(f"[bench] {name}: {vms:.3f} ms/step; range_compress {vstage['range_compress']:.3f} ms; "
                 f"backproject {vstage['backproject']:.3f} ms")
