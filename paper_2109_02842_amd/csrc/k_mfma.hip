@@ -142,9 +142,27 @@ __device__ __forceinline__ unsigned short bf16_of(float x) {
     return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
 }
 
+// 16-byte direct global-to-LDS copy (device pass only; the host pass of
+// this translation unit emits the launch stubs and must not see it).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PL_DMA16(SRC, DST) __builtin_amdgcn_global_load_lds((SRC), (DST), 16, 0, 0)
+#else
+#define PL_DMA16(SRC, DST) ((void)(SRC), (void)(DST))
+#endif
+
+// LDS bytes of range_mfma_kernel: two buffers of one channel tile's
+// strengths (32 channels x 4 parts x n_fp values).
+__host__ __device__ constexpr int range_mfma_lds(int n_fp) { return 2 * 32 * 4 * n_fp * 2; }
+
 // One block = one k_z bin x 128 range samples; wavefront w owns rows
 // [32 w, 32 w + 32) of that range block and keeps its phasor operand A' for
-// all of K' in registers, then walks the channel tiles of 32.
+// all of K' in registers, then walks the channel tiles of 32.  The four
+// wavefronts share each tile's strengths: the block copies them into LDS
+// (16-byte direct copies, one tile ahead, double-buffered; chunk j of
+// channel c at position j ^ (c & S) of the channel's row, so that lanes of
+// consecutive channels read distinct banks).  The blocks of one k_z bin run
+// on one XCD (block b runs on XCD b mod 8): the bin's strengths come from
+// memory into that XCD's L2 once.
 // OUT: kOutC64 complex64 profiles; kOutSplit four BF16 planes per
 // (channel, k_z) -- Re hi, Re lo, Im hi, Im lo with x = hi + lo -- the
 // operand layout of the split matrix-core back-projection; kOutF16 two FP16
@@ -161,9 +179,16 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
     typedef typename Half<F16>::V V;
     constexpr int NC = NCH;          // chunks of 16 in K' = 2 n_fp, NC = n_fp / 8
     constexpr int HC = NC / 2;       // chunks per half (Re part / Im part)
+    constexpr int NFP = 8 * NCH;     // padded frequencies (a.n_fp)
+    constexpr int CPC = NFP / 2;     // 16-byte chunks per channel (4 parts)
+    constexpr int SWZ = CPC % 16 == 0 ? 15 : 7;
+    constexpr int NDMA = 32 * CPC / 256;   // copies per thread and tile
+    static_assert(32 * CPC % 256 == 0, "a tile is a whole number of block-wide copies");
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int n_ib = (a.n_l + 127) / 128;
-    const int kap = blockIdx.x / n_ib;
-    const int ib = blockIdx.x - kap * n_ib;
+    const int slot = blockIdx.x >> 3;
+    const int kap = (slot / n_ib) * 8 + (blockIdx.x & 7);
+    const int ib = slot % n_ib;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = ib * 128 + wave * 32;
     int gexp = 0;
@@ -171,7 +196,28 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
         gexp = profile_scale(qexp, log2_nf);
         if (blockIdx.x == 0 && threadIdx.x == 0) qexp[kProfileScaleParts] = gexp;
     }
-    if (row0 >= a.n_l) return;  // no barriers in this kernel
+    if (kap >= a.n_z) return;   // the whole block, before any barrier
+    const bool active = row0 < a.n_l;   // wavefronts past n_l only copy
+    const int n_ct = a.n_chp / 32;
+
+    // copies of tile ct into buffer ct & 1: thread t's j-th copy fills LDS
+    // chunk p = (4 j + wave) * 64 + lane, channel p / CPC, swizzled chunk
+    // p % CPC, from the channel's chunk (p % CPC) ^ (channel & SWZ)
+    const char* tile0 = reinterpret_cast<const char*>(cs + static_cast<size_t>(kap) * a.n_chp * 4 * NFP);
+    unsigned soff[NDMA];
+#pragma unroll
+    for (int j = 0; j < NDMA; ++j) {
+        const int pch = (4 * j + wave) * 64 + lane;
+        const int ch = pch / CPC, js = pch - ch * CPC;
+        soff[j] = static_cast<unsigned>((ch * CPC + (js ^ (ch & SWZ))) * 16);
+    }
+    auto stage = [&](int ct) {
+        const char* src = tile0 + static_cast<size_t>(ct) * 32 * CPC * 16;
+        unsigned char* dst = smem + (ct & 1) * (32 * CPC * 16);
+#pragma unroll
+        for (int j = 0; j < NDMA; ++j) PL_DMA16(src + soff[j], dst + (4 * j + wave) * 1024);
+    };
+    stage(0);
     const int i = row0 + (lane & 31);
     const int kh = 8 * (lane >> 5);  // this lane's k' offset inside a chunk
 
@@ -201,18 +247,23 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
         }
     }
 
-    const int n_ct = a.n_chp / 32;
+    const int cl = lane & 31;   // this lane's channel in the tile
     for (int ct = 0; ct < n_ct; ++ct) {
-        const int c = ct * 32 + (lane & 31);
-        const u32x4* base = reinterpret_cast<const u32x4*>(cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp);
-        const int stride4 = a.n_fp / 8;  // u32x4 per part
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();   // tile ct in LDS; every wavefront done with tile ct - 1
+        if (ct + 1 < n_ct) stage(ct + 1);
+        if (!active) continue;
+        const int c = ct * 32 + cl;
+        const u32x4* base = reinterpret_cast<const u32x4*>(smem + (ct & 1) * (32 * CPC * 16)) + cl * CPC;
+        constexpr int stride4 = NFP / 8;  // chunks per part
         f32x16 accr = {}, acci = {};
 #pragma unroll
         for (int qq = 0; qq < NC; ++qq) {
             const bool second = qq >= HC;
             const int f0 = 16 * (second ? qq - HC : qq) + kh;
-            const u32x4 rh = base[0 * stride4 + f0 / 8], rl = base[1 * stride4 + f0 / 8];
-            const u32x4 ih = base[2 * stride4 + f0 / 8], il = base[3 * stride4 + f0 / 8];
+            const int sw = cl & SWZ;
+            const u32x4 rh = base[(0 * stride4 + f0 / 8) ^ sw], rl = base[(1 * stride4 + f0 / 8) ^ sw];
+            const u32x4 ih = base[(2 * stride4 + f0 / 8) ^ sw], il = base[(3 * stride4 + f0 / 8) ^ sw];
             // Re Q: B' = [Re C; Im C];  Im Q: B'' = [Im C; -Re C]
             const u32x4 b1h = second ? ih : rh, b1l = second ? il : rl;
             const u32x4 b2h = second ? neg16(rh) : ih, b2l = second ? neg16(rl) : il;
@@ -314,12 +365,15 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
         hipLaunchKernelGGL(profile_scale_kernel, dim3(kProfileScaleParts), dim3(256), 0, s, se, static_cast<int>(waves), qexp);
         if ((rc = check_launch("range compression (profile scale)"))) return rc;
     }
-    const long long blocks = static_cast<long long>(p.n_z) * ((p.n_l + 127) / 128);
+    // the blocks of k_z bin kap are (j * n_ib + ib) * 8 + kap % 8 with
+    // j = kap / 8: all on one XCD
+    const long long blocks = 8LL * ((p.n_z + 7) / 8) * ((p.n_l + 127) / 128);
+    const int lds = range_mfma_lds(p.n_fp);
     const double* kp = reinterpret_cast<const double*>(ws + p.off_kp);
     switch (p.n_fp / 8) {
 #define PL_NC(N)                                                                                          \
     case N:                                                                                               \
-        hipLaunchKernelGGL((range_mfma_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, cs, se, \
+        hipLaunchKernelGGL((range_mfma_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks)), dim3(256), lds, s, cs, se, \
                            kp, a, qexp, log2_nf, q);                                                      \
         break;
         PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
