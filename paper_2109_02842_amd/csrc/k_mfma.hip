@@ -159,8 +159,9 @@ __host__ __device__ constexpr int range_mfma_lds(int n_fp) { return 2 * 32 * 4 *
 // all of K' in registers, then walks the channel tiles of 32.  The four
 // wavefronts share each tile's strengths: the block copies them into LDS
 // (16-byte direct copies, one tile ahead, double-buffered; chunk j of
-// channel c at position j ^ (c & S) of the channel's row, so that lanes of
-// consecutive channels read distinct banks).  The blocks of one k_z bin run
+// channel c at position j ^ (c & 15) of the channel's row, c & 7 when the
+// row has an odd multiple of 8 chunks, so that the lanes of consecutive
+// channels read distinct banks).  The blocks of one k_z bin run
 // on one XCD (block b runs on XCD b mod 8): the bin's strengths come from
 // memory into that XCD's L2 once.
 // OUT: kOutC64 complex64 profiles; kOutSplit four BF16 planes per
