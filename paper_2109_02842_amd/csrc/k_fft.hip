@@ -268,13 +268,13 @@ int resident_grid(const void* fn, size_t smem, const char* what, long long group
 // The same batched strided FFT for N = 64 R (R at most 8) on the wavefront
 // FFT (wave_ifft): a workgroup stages TB transforms in LDS with loads and
 // stores that run along whichever of (transform, element) is contiguous in
-// memory (TB = 8: 64-byte runs across transforms), its four wavefronts
+// memory (TB = 16: 128-byte runs across transforms), its NW wavefronts
 // transform them in place (wave_ifft's last radix-8 pass is a single pass
 // for R <= 8, so every lane has read its inputs before any output lands),
 // and the forward direction conjugates on the way in and out.  Transforms
 // are kWaveRow R + 2 values apart in LDS: 4 dwords of bank offset apiece.
-template <int R, int TB>
-__global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __restrict__ in,
+template <int R, int TB, int NW>
+__global__ __launch_bounds__(64 * NW) void fft_wave_strided_kernel(const float2* __restrict__ in,
                                                                float2* __restrict__ out,
                                                                const float2* __restrict__ tw, FftArgs a) {
     constexpr int N = 64 * R;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __r
     const int nb = min(TB, a.nbatch - b0);
     const int tid = threadIdx.x;
     const bool fwd = a.sign < 0;
-    for (int e = tid; e < TB * N; e += 256) {
+    for (int e = tid; e < TB * N; e += 64 * NW) {
         int t, i;
         if (a.n_fast_in) {
             t = e / N;
@@ -303,12 +303,12 @@ __global__ __launch_bounds__(256) void fft_wave_strided_kernel(const float2* __r
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
-    for (int t = wave; t < nb; t += 4) {
+    for (int t = wave; t < nb; t += NW) {
         float2* A = smem + t * PS;
         wave_ifft<R>(A, tw, lane, [&](int k, float2 v) { A[k] = v; });
     }
     __syncthreads();
-    for (int e = tid; e < TB * N; e += 256) {
+    for (int e = tid; e < TB * N; e += 64 * NW) {
         int t, i;
         if (a.n_fast_out) {
             t = e / N;
@@ -558,18 +558,19 @@ int launch_chirp_wave(const FftArgs& a, const float2* in, float2* out, const flo
 template <int R>
 int launch_fft_wave(const FftArgs& a, const float2* in, float2* out, const float2* tw, hipStream_t s,
                     const char* what) {
-    // eight transforms per workgroup: 64-byte runs on the strided side and
-    // eight resident workgroups per CU at R = 4 (sixteen transforms, with
-    // 128-byte runs but half the workgroups, ran 15-20 % slower)
-    constexpr int TB = 8;
+    // sixteen transforms per workgroup of eight wavefronts: 128-byte runs on
+    // the strided side (measured 10 % faster than eight transforms on four
+    // wavefronts with 64-byte runs; sixteen on four wavefronts, half the
+    // resident wavefronts, had run 15-20 % slower)
+    constexpr int TB = 16, NW = 8;
     const size_t smem = static_cast<size_t>(TB) * (kWaveRow * R + 2) * sizeof(float2);
-    auto fn = fft_wave_strided_kernel<R, TB>;
+    auto fn = fft_wave_strided_kernel<R, TB, NW>;
     if (smem > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             static_cast<int>(smem)) != hipSuccess)
         return fail(PL_EDEVICE, "%s: LDS of %zu bytes refused", what, smem);
     const long long blocks = (static_cast<long long>(a.nbatch) + TB - 1) / TB;
-    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(256), smem, s, in, out, tw, a);
+    hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(64 * NW), smem, s, in, out, tw, a);
     return check_launch(what);
 }
 
