@@ -55,10 +55,12 @@ struct MfmaArgs {
     double du;
 };
 
-// Strengths C[f][c] for one (k_z, channel) per wavefront, split into
-// hi / lo parts of Re and Im: cs[((kz * n_chp + c) * 4 + part) * n_fp + f],
-// part 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo; padded frequencies and channels
-// are zero.  se[kz * n_chp + c] is the power-of-2 scale exponent.
+// Strengths C[f][c] of one channel and kStrengthBins consecutive k_z bins
+// per wavefront (every load of the bins issued before the arithmetic),
+// split into hi / lo parts of Re and Im: cs[((kz * n_chp + c) * 4 + part) *
+// n_fp + f], part 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo; padded frequencies and
+// channels are zero.  se[kz * n_chp + c] is the power-of-2 scale exponent.
+constexpr int kStrengthBins = 4;
 template <bool F16>
 __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict__ spec,
                                                         const double* __restrict__ llo,
@@ -67,48 +69,68 @@ __global__ __launch_bounds__(256) void strengths_kernel(const float2* __restrict
                                                         typename Half<F16>::T* __restrict__ cs,
                                                         int* __restrict__ se) {
     typedef typename Half<F16>::T T;
+    constexpr int KB = kStrengthBins;
     const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (wid >= a.n_z * a.n_chp) return;
-    const int kap = wid / a.n_chp, c = wid - kap * a.n_chp;
-    float2 v[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};  // n_fp <= 128
-    float mx = 0.f;
-    if (c < a.n_ch) {
-        const double lmid = llo[c] + (a.n_l / 2) * a.du;
+    const int n_groups = (a.n_z + KB - 1) / KB;
+    if (wid >= n_groups * a.n_chp) return;
+    const int kap0 = (wid / a.n_chp) * KB, c = wid % a.n_chp;
+    float2 s[KB][2], v[KB][2];
+    double kpf[KB][2];
+    float w[KB][2];
+    const bool chan = c < a.n_ch;
+    const double lmid = chan ? llo[c] + (a.n_l / 2) * a.du : 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        const int kap = kap0 + j;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int f = lane + 64 * h;
-            if (f < a.n_f) {
+            const int f = lane + 64 * h;   // n_fp <= 128
+            s[j][h] = make_float2(0.f, 0.f);
+            kpf[j][h] = 0.0;
+            w[j][h] = 0.f;
+            if (chan && kap < a.n_z && f < a.n_f) {
                 const size_t e = static_cast<size_t>(kap) * a.n_f + f;
-                const float2 s = spec[(static_cast<size_t>(c) * a.n_z + kap) * a.n_f + f];
-                v[h] = cscale(cmul(s, cis(kp[e] * lmid)), wk[e]);
-                mx = fmaxf(mx, fmaxf(fabsf(v[h].x), fabsf(v[h].y)));
+                s[j][h] = spec[(static_cast<size_t>(c) * a.n_z + kap) * a.n_f + f];
+                kpf[j][h] = kp[e];
+                w[j][h] = wk[e];
             }
         }
     }
-    int ex = 0;
-    if (F16) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        // all-zero pairs (padding, evanescent k_z) take the largest exponent,
-        // so they never decide the single-pass scale below
-        ex = mx > 0.f ? min(max(14 - ilogbf(mx), -100), 100) : 100;
-    }
-    const float sc = ldexpf(1.f, ex);
-    T* dst = cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp;
+    for (int j = 0; j < KB; ++j) {
+        const int kap = kap0 + j;
+        if (kap >= a.n_z) break;   // wavefront-uniform
+        float mx = 0.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int f = lane + 64 * h;
-        if (f < a.n_fp) {
-            const float re = v[h].x * sc, im = v[h].y * sc;
-            const T rh = static_cast<T>(re), ih = static_cast<T>(im);
-            dst[f] = rh;
-            dst[a.n_fp + f] = static_cast<T>(re - static_cast<float>(rh));
-            dst[2 * a.n_fp + f] = ih;
-            dst[3 * a.n_fp + f] = static_cast<T>(im - static_cast<float>(ih));
+        for (int h = 0; h < 2; ++h) {
+            v[j][h] = cscale(cmul(s[j][h], cis(kpf[j][h] * lmid)), w[j][h]);
+            mx = fmaxf(mx, fmaxf(fabsf(v[j][h].x), fabsf(v[j][h].y)));
         }
+        int ex = 0;
+        if (F16) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            // all-zero pairs (padding, evanescent k_z) take the largest
+            // exponent, so they never decide the single-pass scale below
+            ex = mx > 0.f ? min(max(14 - ilogbf(mx), -100), 100) : 100;
+        }
+        const float sc = ldexpf(1.f, ex);
+        T* dst = cs + (static_cast<size_t>(kap) * a.n_chp + c) * 4 * a.n_fp;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = lane + 64 * h;
+            if (f < a.n_fp) {
+                const float re = v[j][h].x * sc, im = v[j][h].y * sc;
+                const T rh = static_cast<T>(re), ih = static_cast<T>(im);
+                dst[f] = rh;
+                dst[a.n_fp + f] = static_cast<T>(re - static_cast<float>(rh));
+                dst[2 * a.n_fp + f] = ih;
+                dst[3 * a.n_fp + f] = static_cast<T>(im - static_cast<float>(ih));
+            }
+        }
+        if (lane == 0) se[static_cast<size_t>(kap) * a.n_chp + c] = ex;
     }
-    if (lane == 0) se[wid] = ex;
 }
 
 __device__ __forceinline__ u32x4 neg16(u32x4 x) { return x ^ 0x80008000u; }
@@ -353,8 +375,9 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
     a.du = p.du;
     T* cs = reinterpret_cast<T*>(ws + p.off_mfma_b);
     int* se = reinterpret_cast<int*>(ws + p.off_mfma_a);
-    const long long waves = static_cast<long long>(p.n_z) * p.n_chp;
-    hipLaunchKernelGGL(strengths_kernel<F16>, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, s, spec,
+    const long long waves = static_cast<long long>(p.n_z) * p.n_chp;   // (k_z, channel) pairs
+    const long long swaves = static_cast<long long>((p.n_z + kStrengthBins - 1) / kStrengthBins) * p.n_chp;
+    hipLaunchKernelGGL(strengths_kernel<F16>, dim3(static_cast<unsigned>((swaves + 3) / 4)), dim3(256), 0, s, spec,
                        reinterpret_cast<const double*>(ws + p.off_llo), reinterpret_cast<const double*>(ws + p.off_kp),
                        reinterpret_cast<const float*>(ws + p.off_wk), a, cs, se);
     int rc = check_launch("range compression (strengths)");
