@@ -221,9 +221,15 @@ def test_range_compress_every_wavefront_radix(n_fine):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-@pytest.mark.parametrize("wlname", ["tiny-mono", "multi-small", "C1"])
+@pytest.mark.parametrize("wlname", ["tiny-mono", "multi-small", "C1", "C1-40f", "C1-100f"])
 def test_mfma_range_compress_matches_direct_nudft(precision, wlname):
-    wl = {"tiny-mono": W.tiny("mono"), "multi-small": multi_small(), "C1": W.C1}[wlname]
+    # 40 and 100 frequencies pad to 48 and 112 (strength rows of 24 and 56
+    # chunks: the 8-chunk swizzle), 16 and 64 to rows of 8 and 32 chunks;
+    # the C1 range grid of these plans (n_l 192) leaves the last 128-row
+    # block's third and fourth wavefronts without rows
+    wl = {"tiny-mono": W.tiny("mono"), "multi-small": multi_small(), "C1": W.C1,
+          "C1-40f": replace(W.C1, array=replace(W.C1.array, n_freq=40)),
+          "C1-100f": replace(W.C1, array=replace(W.C1.array, n_freq=100))}[wlname]
     g = pr.make_geometry(wl.array)
     plan = pr.hybrid_plan_info(g, wl.grid, precision=precision, mfma_backprojection=-1)
     s = W.random_echo(wl.array, 9)
