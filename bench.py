@@ -16,6 +16,7 @@ import math
 import os
 import sys
 import time
+from dataclasses import replace
 
 import numpy as np
 
@@ -326,6 +327,27 @@ def bench_c3(args, torch, pr, W):
             res["adjoint"] = {"ms_per_call": ams, "voxels_per_s": voxels / (ams * 1e-3),
                               "note": "image -> echo, FP32, NUFFT plan with the pixel-per-lane kernel"}
             log(f"[bench] C3 adjoint: {ams:.3f} ms per call")
+        # One GPU's share of the chord-sharded reconstruction: the middle
+        # chord's channels (one of seven) at the full pixel and k_z shape.
+        # A run over seven GPUs would add one reduce-scatter of the spectrum
+        # by pixel rows before the k_z transform, which is not built here.
+        a1 = replace(a, n_chords=1)
+        wl1 = replace(wl, array=a1)
+        geom1 = pr.make_geometry(a1)
+        echo1 = pr.simulate_echo(geom1, torch.from_numpy(pos).cuda(), torch.from_numpy(refl).cuda())
+        torch.cuda.synchronize()
+        time1, _ = make_timers(pr, torch, W, wl1, geom1, echo1, img)
+        share = {"channels": geom1.n_channels,
+                 "note": "middle chord of C3 at the full 256x256x512 shape; per-GPU compute of a 7-GPU "
+                         "chord-sharded run (its reduce-scatter of the spectrum is not built)"}
+        for name, opts in paths:
+            ms1, st1, _, med1, _ = time1(opts, steps, 2, min_warm_s=0.3)
+            share[name] = {"ms_per_step": ms1, "median_ms": med1, "stages_ms": st1,
+                           "fraction_of_full": ms1 / res[name]["ms_per_step"]}
+            log(f"[bench] C3 one chord ({geom1.n_channels} channels) {name}: {ms1:.3f} ms/step, "
+                f"{ms1 / res[name]['ms_per_step']:.3f} of the full array")
+        res["one_chord_share"] = share
+        del echo1
     if not args.no_parity:
         for name, opts in paths:
             r = res[name]
