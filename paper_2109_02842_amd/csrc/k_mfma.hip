@@ -29,6 +29,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool F16>
@@ -40,6 +41,9 @@ struct Half<false> {
     static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
 };
 template <>
 struct Half<true> {
@@ -47,6 +51,9 @@ struct Half<true> {
     typedef f16x8 V;
     static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
     }
 };
 
@@ -362,6 +369,187 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
     }
 }
 
+// The same contraction for wide frequency sets (n_fp > 64), where the
+// 32-row form's phasor registers leave one wavefront per SIMD: a wavefront
+// owns 16 rows (v_mfma_f32_16x16x32: lane l holds row or column l & 15 and
+// K' values 8 (l / 16) .. + 7 of a chunk of 32; the result rows 4 (l / 16)
+// .. + 3 of column l & 15), a block of four wavefronts 64 rows, and the
+// channel tiles are 16 wide, staged in LDS as in range_mfma_kernel.
+constexpr int kRows16 = 64;
+__host__ __device__ constexpr int range_mfma16_lds(int n_fp) { return 2 * 16 * 4 * n_fp * 2; }
+template <bool F16, int NCH, int OUT>
+__global__ __launch_bounds__(256) void range_mfma16_kernel(const typename Half<F16>::T* __restrict__ cs,
+                                                           const int* __restrict__ se,
+                                                           const double* __restrict__ kp, MfmaArgs a,
+                                                           int* __restrict__ qexp, int log2_nf,
+                                                           void* __restrict__ qout) {
+    typedef typename Half<F16>::T T;
+    typedef typename Half<F16>::V V;
+    constexpr int NFP = 8 * NCH;          // padded frequencies (a.n_fp)
+    constexpr int NQ = NCH / 2;           // chunks of 32 in K' = 2 n_fp
+    constexpr int CPC = NFP / 2;          // 16-byte chunks per channel (4 parts)
+    constexpr int SWZ = CPC % 16 == 0 ? 15 : 7;
+    constexpr int TILE = 16 * CPC;        // chunks per channel tile
+    constexpr int NDMA = (TILE + 255) / 256;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int n_ib = (a.n_l + kRows16 - 1) / kRows16;
+    const int slot = blockIdx.x >> 3;
+    const int kap = (slot / n_ib) * 8 + (blockIdx.x & 7);
+    const int ib = slot % n_ib;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = ib * kRows16 + wave * 16;
+    int gexp = 0;
+    if constexpr (OUT == kOutF16) {
+        gexp = profile_scale(qexp, log2_nf);
+        if (blockIdx.x == 0 && threadIdx.x == 0) qexp[kProfileScaleParts] = gexp;
+    }
+    if (kap >= a.n_z) return;   // the whole block, before any barrier
+    const bool active = row0 < a.n_l;
+    const int n_ct = a.n_chp / 16;
+
+    // copies of tile ct into buffer ct & 1: thread t's j-th copy fills LDS
+    // chunk p = (4 j + wave) * 64 + lane (lanes past the tile idle)
+    const char* tile0 = reinterpret_cast<const char*>(cs + static_cast<size_t>(kap) * a.n_chp * 4 * NFP);
+    unsigned soff[NDMA];
+#pragma unroll
+    for (int j = 0; j < NDMA; ++j) {
+        const int pch = (4 * j + wave) * 64 + lane;
+        const int ch = pch / CPC, js = pch - ch * CPC;
+        soff[j] = pch < TILE ? static_cast<unsigned>((ch * CPC + (js ^ (ch & SWZ))) * 16) : ~0u;
+    }
+    auto stage = [&](int ct) {
+        const char* src = tile0 + static_cast<size_t>(ct) * TILE * 16;
+        unsigned char* dst = smem + (ct & 1) * (TILE * 16);
+#pragma unroll
+        for (int j = 0; j < NDMA; ++j)
+            if ((4 * j + wave) * 64 < TILE && soff[j] != ~0u) PL_DMA16(src + soff[j], dst + (4 * j + wave) * 1024);
+    };
+    stage(0);
+    const int i = row0 + (lane & 15);
+    const int kh = 8 * (lane >> 4);   // this lane's k' offset inside a chunk
+
+    // phasor operand: the lane's 8 values of chunk q are k' = 32 q + kh + t;
+    // k' < n_fp holds Re A at f = k', k' >= n_fp holds -Im A at f = k' - n_fp
+    V ah[NQ], al[NQ];
+    {
+        const double u = (i - a.n_l / 2) * a.du;
+        const bool row_ok = i < a.n_l;
+        const double* kprow = kp + static_cast<size_t>(kap) * a.n_f;
+        auto put = [&](int q, int t, float x) {
+            const T xh = static_cast<T>(x);
+            ah[q][t] = xh;
+            al[q][t] = static_cast<T>(x - static_cast<float>(xh));
+        };
+        if constexpr (NFP % 32 == 0) {
+            // chunk q + NQ / 2 holds -Im A at the frequencies of chunk q
+#pragma unroll
+            for (int q = 0; q < NQ / 2; ++q) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int f = 32 * q + kh + t;
+                    float2 e = make_float2(0.f, 0.f);
+                    if (row_ok && f < a.n_f) e = cis(kprow[f] * u);
+                    put(q, t, e.x);
+                    put(q + NQ / 2, t, -e.y);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int k0 = 32 * q + kh;
+                const bool im = k0 >= NFP;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int f = (im ? k0 - NFP : k0) + t;
+                    float2 e = make_float2(0.f, 0.f);
+                    if (row_ok && f < a.n_f) e = cis(kprow[f] * u);
+                    put(q, t, im ? -e.y : e.x);
+                }
+            }
+        }
+    }
+
+    const int cl = lane & 15;   // this lane's channel in the tile
+    for (int ct = 0; ct < n_ct; ++ct) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();   // tile ct in LDS; every wavefront done with tile ct - 1
+        if (ct + 1 < n_ct) stage(ct + 1);
+        if (!active) continue;
+        const int c = ct * 16 + cl;
+        const u32x4* base = reinterpret_cast<const u32x4*>(smem + (ct & 1) * (TILE * 16)) + cl * CPC;
+        constexpr int stride4 = NFP / 8;   // chunks per part
+        const int sw = cl & SWZ;
+        f32x4 accr = {}, acci = {};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int k0 = 32 * q + kh;
+            const bool second = k0 >= NFP;
+            const int f0 = second ? k0 - NFP : k0;
+            const u32x4 rh = base[(0 * stride4 + f0 / 8) ^ sw], rl = base[(1 * stride4 + f0 / 8) ^ sw];
+            const u32x4 ih = base[(2 * stride4 + f0 / 8) ^ sw], il = base[(3 * stride4 + f0 / 8) ^ sw];
+            // Re Q: B' = [Re C; Im C];  Im Q: B'' = [Im C; -Re C]
+            const u32x4 b1h = second ? ih : rh, b1l = second ? il : rl;
+            const u32x4 b2h = second ? neg16(rh) : ih, b2l = second ? neg16(rl) : il;
+            const V vb1h = __builtin_bit_cast(V, b1h), vb1l = __builtin_bit_cast(V, b1l);
+            const V vb2h = __builtin_bit_cast(V, b2h), vb2l = __builtin_bit_cast(V, b2l);
+            accr = Half<F16>::mfma16(ah[q], vb1h, accr);
+            accr = Half<F16>::mfma16(ah[q], vb1l, accr);
+            accr = Half<F16>::mfma16(al[q], vb1h, accr);
+            acci = Half<F16>::mfma16(ah[q], vb2h, acci);
+            acci = Half<F16>::mfma16(ah[q], vb2l, acci);
+            acci = Half<F16>::mfma16(al[q], vb2h, acci);
+        }
+        if (c >= a.n_ch) continue;
+        const int ex = se[static_cast<size_t>(kap) * a.n_chp + c];
+        const int r = row0 + 4 * (lane >> 4);   // rows r .. r + 3 of column c
+        if constexpr (OUT == kOutF16) {
+            // n_l is a multiple of 4: the four rows are all in range or all out
+            if (r < a.n_l) {
+                const float sc = ldexpf(1.f, -ex - gexp);
+                _Float16* dst = static_cast<_Float16*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 2 * a.n_l;
+                typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+                h4 vr, vi;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    vr[k] = static_cast<_Float16>(accr[k] * sc);
+                    vi[k] = static_cast<_Float16>(acci[k] * sc);
+                }
+                *reinterpret_cast<h4*>(dst + r) = vr;
+                *reinterpret_cast<h4*>(dst + a.n_l + r) = vi;
+            }
+        } else if constexpr (OUT == kOutSplit) {
+            if (r < a.n_l) {
+                const float sc = ldexpf(1.f, -ex);
+                unsigned short* dst =
+                    static_cast<unsigned short*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * 4 * a.n_l;
+                unsigned short rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float xr = accr[k] * sc, xi = acci[k] * sc;
+                    rh[k] = bf16_of(xr);
+                    ih[k] = bf16_of(xi);
+                    rl[k] = bf16_of(xr - __uint_as_float(static_cast<unsigned>(rh[k]) << 16));
+                    il[k] = bf16_of(xi - __uint_as_float(static_cast<unsigned>(ih[k]) << 16));
+                }
+                auto pack = [](const unsigned short (&h)[4]) {
+                    return make_uint2(h[0] | (static_cast<unsigned>(h[1]) << 16),
+                                      h[2] | (static_cast<unsigned>(h[3]) << 16));
+                };
+                *reinterpret_cast<uint2*>(dst + r) = pack(rh);
+                *reinterpret_cast<uint2*>(dst + a.n_l + r) = pack(rl);
+                *reinterpret_cast<uint2*>(dst + 2 * a.n_l + r) = pack(ih);
+                *reinterpret_cast<uint2*>(dst + 3 * a.n_l + r) = pack(il);
+            }
+        } else {
+            const float sc = ldexpf(1.f, -ex);
+            float2* dst = static_cast<float2*>(qout) + (static_cast<size_t>(c) * a.n_z + kap) * a.n_l;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (r + k < a.n_l) dst[r + k] = make_float2(accr[k] * sc, acci[k] * sc);
+        }
+    }
+}
+
 template <bool F16, int OUT>
 int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStream_t s) {
     typedef typename Half<F16>::T T;
@@ -394,14 +582,24 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
     const long long blocks = 8LL * ((p.n_z + 7) / 8) * ((p.n_l + 127) / 128);
     const int lds = range_mfma_lds(p.n_fp);
     const double* kp = reinterpret_cast<const double*>(ws + p.off_kp);
+    // wide frequency sets: 16-row wavefronts (the 32-row form's phasor
+    // registers would leave one wavefront per SIMD)
+    const long long blocks16 = 8LL * ((p.n_z + 7) / 8) * ((p.n_l + kRows16 - 1) / kRows16);
+    const int lds16 = range_mfma16_lds(p.n_fp);
     switch (p.n_fp / 8) {
 #define PL_NC(N)                                                                                          \
     case N:                                                                                               \
         hipLaunchKernelGGL((range_mfma_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks)), dim3(256), lds, s, cs, se, \
                            kp, a, qexp, log2_nf, q);                                                      \
         break;
-        PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC(10) PL_NC(12) PL_NC(14) PL_NC(16)
+#define PL_NC16(N)                                                                                        \
+    case N:                                                                                               \
+        hipLaunchKernelGGL((range_mfma16_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks16)), dim3(256), lds16, s, \
+                           cs, se, kp, a, qexp, log2_nf, q);                                              \
+        break;
+        PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC16(10) PL_NC16(12) PL_NC16(14) PL_NC16(16)
 #undef PL_NC
+#undef PL_NC16
         default:
             return fail(PL_EUNSUPPORTED, "MFMA range compression supports up to 128 frequencies");
     }
