@@ -369,8 +369,8 @@ __global__ __launch_bounds__(256) void range_mfma_kernel(const typename Half<F16
     }
 }
 
-// The same contraction for wide frequency sets (n_fp > 64), where the
-// 32-row form's phasor registers leave one wavefront per SIMD: a wavefront
+// The same contraction for 64 or more frequencies, where the 32-row
+// form's phasor registers leave one or two wavefronts per SIMD: a wavefront
 // owns 16 rows (v_mfma_f32_16x16x32: lane l holds row or column l & 15 and
 // K' values 8 (l / 16) .. + 7 of a chunk of 32; the result rows 4 (l / 16)
 // .. + 3 of column l & 15), a block of four wavefronts 64 rows, and the
@@ -582,8 +582,9 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
     const long long blocks = 8LL * ((p.n_z + 7) / 8) * ((p.n_l + 127) / 128);
     const int lds = range_mfma_lds(p.n_fp);
     const double* kp = reinterpret_cast<const double*>(ws + p.off_kp);
-    // wide frequency sets: 16-row wavefronts (the 32-row form's phasor
-    // registers would leave one wavefront per SIMD)
+    // 64 or more frequencies: 16-row wavefronts (the 32-row form's phasor
+    // registers leave two wavefronts per SIMD at 64 and one at 128; the
+    // 16-row form keeps three to five)
     const long long blocks16 = 8LL * ((p.n_z + 7) / 8) * ((p.n_l + kRows16 - 1) / kRows16);
     const int lds16 = range_mfma16_lds(p.n_fp);
     switch (p.n_fp / 8) {
@@ -597,7 +598,7 @@ int run_mfma(const HybridPlan& p, const float2* spec, char* ws, void* q, hipStre
         hipLaunchKernelGGL((range_mfma16_kernel<F16, N, OUT>), dim3(static_cast<unsigned>(blocks16)), dim3(256), lds16, s, \
                            cs, se, kp, a, qexp, log2_nf, q);                                              \
         break;
-        PL_NC(2) PL_NC(4) PL_NC(6) PL_NC(8) PL_NC16(10) PL_NC16(12) PL_NC16(14) PL_NC16(16)
+        PL_NC(2) PL_NC(4) PL_NC(6) PL_NC16(8) PL_NC16(10) PL_NC16(12) PL_NC16(14) PL_NC16(16)
 #undef PL_NC
 #undef PL_NC16
         default:
