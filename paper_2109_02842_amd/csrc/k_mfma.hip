@@ -8,7 +8,10 @@
 //   Re Q = A' [Re C; Im C],   Im Q = A' [Im C; -Re C].
 // Operands are BF16 or FP16 split into hi + lo parts (x = hi + lo, each
 // rounded to nearest), and each product is hi*hi + hi*lo + lo*hi with FP32
-// accumulation in the matrix cores (v_mfma_f32_32x32x16_{bf16,f16}).  The
+// accumulation in the matrix cores (v_mfma_f32_32x32x16_{bf16,f16} on
+// 32-row wavefronts below 64 frequencies, v_mfma_f32_16x16x32 on 16-row
+// wavefronts from 64 up, where the phasor operand's registers would
+// otherwise leave one or two wavefronts per SIMD).  The
 // phasor phase k'_f u_i is formed in float64 and range-reduced before the
 // float32 sin/cos.  FP16 strengths carry a power-of-2 scale per (k_z,
 // channel) so their largest part sits near 2^14.
